@@ -1,0 +1,249 @@
+/*
+ * cvo.h -- C ABI of the MI355X (gfx950) implementation of continuous RKHS
+ * point-cloud registration ("CVO", arXiv 2012.03683: "A New Framework for
+ * Registration of Semantic Point Clouds from Stereo and RGB-D Cameras").
+ *
+ * Notation (the paper's):
+ *   X = {x_i}, Z = {z_j} subset R^3 with feature vectors u_i = l_X(x_i),
+ *   v_j = l_Z(z_j)  (Sec. III).  A pose T = (R, t) maps Z-frame coordinates
+ *   into the X frame, z'_j = R z_j + t; it plays the role of h^-1 in
+ *   Problem 1, so F(T) = <f_X, f_{T Z}>.
+ *   k(x, z) = sigma^2 exp(-|x - z|^2 / (2 ell^2))                (eq. (2))
+ *   c_ij = prod_b k_b(u_i^(b), v_j^(b)), k_b squared-exponential  (eq. (5))
+ *          or linear <u, v> (eq. (4)); blocks combine as a tensor
+ *          product (eq. (6)); no blocks means c = 1 (eq. (8)).
+ *   F(T) = sum_{(i,j) in P} c_ij k(x_i, z'_j)                     (eq. (7))
+ *   P = {(i,j) : s_ij <= (kappa ell)^2}, s_ij = |x_i - z'_j|^2, the
+ *       truncation of the sparse double sum (Sec. III-B); kappa = +inf
+ *       keeps every pair.  Membership is decided exactly as the FP64
+ *       expression s = (dx*dx + dy*dy) + dz*dz with
+ *       z'_r = ((R_r0 z_0 + R_r1 z_1) + R_r2 z_2) + t_r, every operation a
+ *       separately rounded IEEE double (no fused multiply-add), so |P| is
+ *       reproducible bit for bit.
+ *   i_theta = F / sqrt(|X| |Z|)                                   (eq. (10))
+ *   gradient: grad = (omega, v) = d/dxi F(Exp(xi) T) at xi = 0 (left
+ *       perturbation on se(3)); the paper states no formula -- it is the
+ *       derivative of eq. (7) with c_ij constant (Sec. III-B):
+ *       omega = ell^-2 sum w (z' x d), v = ell^-2 sum w d, d = x - z'.
+ *
+ * Memory and ownership
+ *   - cvo_cloud buffers, backward outputs and the batched T arrays marked
+ *     "device" are DEVICE pointers on the handle's device (float32,
+ *     contiguous, row-major).  The caller owns them; the library never
+ *     frees or retains them past the call.
+ *   - Poses, scalars, reports and traces are HOST pointers, owned by the
+ *     caller.
+ *   - The handle owns every scratch buffer (grids, moments, partials,
+ *     graphs).  Scratch grows on demand and is released by cvo_destroy.
+ *   - Calls are ordered on the handle's stream and return after the host
+ *     outputs are written (they synchronise that stream).
+ *   - A handle is not thread safe: one call at a time per handle.
+ *
+ * Errors: every call returns a cvo_status; on failure cvo_last_error()
+ * gives a message.  N = 0 or M = 0 is not an error (F = 0, gradient 0,
+ * |P| = 0; cvo_align reports CVO_NO_OVERLAP and returns T_init).
+ * Non-convergence is a report status, never an error code.
+ */
+#ifndef CVO_H
+#define CVO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cvo_context *cvo_handle;
+
+typedef enum {
+    CVO_OK = 0,
+    CVO_ERR_INVALID_ARGUMENT = 1, /* bad sizes, pointers, non-finite or non-positive parameters */
+    CVO_ERR_OUT_OF_MEMORY = 2,    /* device allocation failed */
+    CVO_ERR_DEVICE = 3,           /* a HIP runtime error; message kept */
+    CVO_ERR_UNSUPPORTED = 4       /* e.g. feature layout beyond the compiled limits */
+} cvo_status;
+
+/* block kernel kinds (eq. (4)-(6)) */
+#define CVO_SE 0
+#define CVO_LIN 1
+#define CVO_MAX_BLOCKS 8
+#define CVO_MAX_FEATURE_DIM 64 /* total feature dimension after combining blocks */
+
+/* registration outcome (cvo_align_report.status) */
+#define CVO_CONVERGED 1  /* lengthscale at its floor and the last step below (eps_rot, eps_trans) */
+#define CVO_MAX_ITER 2   /* iteration cap reached (the normal end in fixed-iteration mode) */
+#define CVO_NO_OVERLAP 3 /* the pair set P became empty */
+#define CVO_STATIONARY 4 /* the gradient is exactly zero */
+
+/* trace record per iteration (cvo_align trace buffer, doubles) */
+#define CVO_TRACE_LEN 8 /* it, ell, F, |grad|, step tau, i_theta, |P|, curvature */
+
+typedef struct {
+    const float *xyz;  /* device, n x 3 */
+    const float *feat; /* device, n x D (D from the feature spec); may be NULL when D = 0 */
+    int64_t n;         /* number of points, >= 0 */
+} cvo_cloud;
+
+/* Feature blocks l(x) = (u_1, u_2, ...) in V_1 x V_2 x ... (Sec. III-B).
+ * Block b occupies dim[b] consecutive columns of feat, in block order. */
+typedef struct {
+    int32_t nblocks;                 /* 0 .. CVO_MAX_BLOCKS */
+    int32_t dim[CVO_MAX_BLOCKS];     /* > 0 */
+    int32_t kind[CVO_MAX_BLOCKS];    /* CVO_SE or CVO_LIN */
+    double ell[CVO_MAX_BLOCKS];      /* SE lengthscale ell_b > 0 (ignored for LIN) */
+    double sigma[CVO_MAX_BLOCKS];    /* SE amplitude sigma_b > 0 (ignored for LIN) */
+} cvo_feature_spec;
+
+typedef struct {
+    double ell;   /* geometric lengthscale > 0 (eq. (2)) */
+    double sigma; /* geometric amplitude > 0 (eq. (2)); 1 makes the Remark of Sec. III-C hold */
+    double kappa; /* cutoff radius in lengthscales, > 0; +inf keeps all pairs */
+} cvo_kernel_params;
+
+typedef struct {
+    double ell_init;     /* starting lengthscale */
+    double ell_min;      /* floor of the annealing schedule (Sec. IV) */
+    double decay;        /* factor applied when the indicator stabilises (0.98: Sec. IV) */
+    double ind_rel_tol;  /* stabilised: |i - i_prev| <= ind_rel_tol * |i| */
+    double eps_rot;      /* convergence: rotation step below this (rad) ... */
+    double eps_trans;    /* ... and translation step below this (m), at ell_min */
+    double step_lambda;  /* step clamp: no point moves more than step_lambda * ell per step */
+    double sigma;        /* geometric amplitude */
+    double kappa;        /* cutoff in lengthscales */
+    int64_t max_iter;    /* iteration cap, >= 1 */
+    int32_t fixed_iters; /* nonzero: run exactly max_iter steps at ell_init, no annealing */
+    int32_t reserved;
+} cvo_align_params;
+
+typedef struct {
+    int64_t iterations;  /* steps taken */
+    double final_ell;    /* lengthscale at exit */
+    double F;            /* F at the last evaluation */
+    double i_theta;      /* indicator at the last evaluation (eq. (10)) */
+    int64_t n_pairs;     /* |P| at the last evaluation */
+    int32_t status;      /* CVO_CONVERGED, CVO_MAX_ITER, CVO_NO_OVERLAP, CVO_STATIONARY */
+    int32_t reserved;
+    int64_t total_pairs; /* sum of |P| over all evaluations of this registration */
+} cvo_align_report;
+
+typedef struct {
+    double F;        /* eq. (7) */
+    double grad[6];  /* omega_xyz, v_xyz (left perturbation) */
+    double curv;     /* d^2/dtau^2 F(Exp(tau grad) T) at tau = 0 (c_ij constant) */
+    double dF_dell;  /* sum w s / ell^3, cutoff radius held fixed */
+    double r_max;    /* max_j |T z_j| */
+    double i_theta;  /* F / sqrt(NM) (eq. (10)) */
+    int64_t n_pairs; /* |P| */
+} cvo_eval;
+
+/* Tuning knobs (picked by cvo_autotune or set by hand). */
+typedef struct {
+    int32_t cluster_max;   /* max query points per cluster: 8, 16, 32 or 64 */
+    double cell_factor;    /* grid cell edge / cutoff radius, in [0.25, 4] */
+    double cluster_factor; /* cluster edge cap / cutoff radius, in [0.05, 2] */
+    double rebuild_ratio;  /* rebuild grids when cutoff < rebuild_ratio * cutoff at build, in (0, 1] */
+    int32_t unroll;        /* iterations enqueued per host check / per captured graph, 1..64 */
+    int32_t reserved;
+} cvo_tuning;
+
+/* Per-handle timing of the dominant kernel, measured with HIP events on the
+ * handle's stream while profiling is enabled (cvo_set_profiling). */
+typedef struct {
+    int64_t pair_launches;     /* pair-pass launches timed */
+    double pair_ms;            /* summed event time of those launches */
+    int64_t pair_count;        /* summed |P| of the timed launches (when known) */
+    int64_t evaluations;       /* pair-pass evaluations, timed or not */
+} cvo_timing;
+
+/* Create a handle on `device` (HIP ordinal) that enqueues on `stream`
+ * (a hipStream_t, or NULL for the default stream).  Returns
+ * CVO_ERR_INVALID_ARGUMENT for a NULL out pointer or a bad ordinal. */
+cvo_status cvo_create(cvo_handle *out, int device, void *stream);
+
+/* Free the handle and all scratch it owns.  NULL is ignored. */
+void cvo_destroy(cvo_handle h);
+
+/* Switch the stream later calls enqueue on (hipStream_t or NULL). */
+cvo_status cvo_set_stream(cvo_handle h, void *stream);
+
+/* Message for the last failing call on this handle ("" if none). */
+const char *cvo_last_error(cvo_handle h);
+
+/* F of eq. (7) at pose T (host double[12], row-major [R|t]) and the exact
+ * pair count |P|.  F and n_pairs are host pointers; n_pairs may be NULL. */
+cvo_status cvo_inner_product(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,
+                             const cvo_feature_spec *spec, const cvo_kernel_params *kp,
+                             const double T[12], double *F, int64_t *n_pairs);
+
+/* F and its se(3) gradient (omega, v) at T (left perturbation; the derivative
+ * of eq. (7) with c_ij constant, Sec. III-B).  grad is host double[6]. */
+cvo_status cvo_gradient(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,
+                        const cvo_feature_spec *spec, const cvo_kernel_params *kp,
+                        const double T[12], double *F, double grad[6], int64_t *n_pairs);
+
+/* Everything one pair pass yields (F, gradient, curvature along the gradient,
+ * dF/dell, r_max, i_theta, |P|) into a host cvo_eval. */
+cvo_status cvo_evaluate(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,
+                        const cvo_feature_spec *spec, const cvo_kernel_params *kp,
+                        const double T[12], cvo_eval *out);
+
+/* Alignment indicator i_theta = F / sqrt(|X||Z|) at (T, ell) (eq. (10),
+ * Sec. III-C); 0 when either cloud is empty. */
+cvo_status cvo_metric(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,
+                      const cvo_feature_spec *spec, const cvo_kernel_params *kp,
+                      const double T[12], double *i_theta);
+
+/* Problem 1 (eq. (1)): gradient ascent on SE(3) from T_init with lengthscale
+ * annealing (Sec. IV).  Per iteration: evaluate F, grad, curvature; step
+ * tau = min(|g|^2 / -curv (if curv < 0, else +inf),
+ *           step_lambda * ell / (|omega| r_max + |v|));
+ * T <- Exp(tau grad) T; when the indicator has stabilised, ell <- max(ell_min,
+ * decay * ell).  T_out (host double[12]) and report (host) receive the
+ * result; trace (host, may be NULL) receives max_iter x CVO_TRACE_LEN
+ * doubles, of which report->iterations rows are written. */
+cvo_status cvo_align(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,
+                     const cvo_feature_spec *spec, const cvo_align_params *ap,
+                     const double T_init[12], double T_out[12], cvo_align_report *report,
+                     double *trace);
+
+/* Hand-written backward of eq. (7) on the pair set frozen at (T, ell): the
+ * derivatives of gF * F with respect to the point positions (dX: N x 3,
+ * dZ: M x 3), the feature vectors (dU: N x D, dV: M x D) -- all device float32
+ * arrays shaped like the inputs -- and the lengthscale (dEll, host double,
+ * cutoff radius held fixed).  Any output pointer may be NULL (not computed). */
+cvo_status cvo_inner_product_backward(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,
+                                      const cvo_feature_spec *spec, const cvo_kernel_params *kp,
+                                      const double T[12], double gF, float *dX, float *dZ,
+                                      float *dU, float *dV, double *dEll);
+
+/* B independent registrations in one device-resident loop (a captured HIP
+ * graph replayed until every pair has finished).  X, Z: host arrays of B
+ * clouds (device buffers); params: host array of B (or 1, shared);
+ * T_init, T_out: host B x 12; reports: host array of B.  Per-pair results
+ * match B separate cvo_align calls up to floating-point summation order. */
+cvo_status cvo_align_batched(cvo_handle h, int32_t B, const cvo_cloud *X, const cvo_cloud *Z,
+                             const cvo_feature_spec *spec, const cvo_align_params *params,
+                             int32_t nparams, const double *T_init, double *T_out,
+                             cvo_align_report *reports);
+
+/* Read / replace the tuning knobs used by later calls. */
+cvo_status cvo_get_tuning(cvo_handle h, cvo_tuning *out);
+cvo_status cvo_set_tuning(cvo_handle h, const cvo_tuning *in);
+
+/* Time a pair pass of (X, Z, spec, kp, T) under each candidate tuning in a
+ * built-in search space and keep the fastest; the choice is cached in the
+ * handle per (point-count, feature-layout, lengthscale band) class.  If
+ * chosen is non-NULL it receives the winner. */
+cvo_status cvo_autotune(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,
+                        const cvo_feature_spec *spec, const cvo_kernel_params *kp,
+                        const double T[12], cvo_tuning *chosen);
+
+/* Enable (nonzero) or disable HIP-event timing of every pair-pass launch;
+ * enabling resets the counters. */
+cvo_status cvo_set_profiling(cvo_handle h, int32_t enable);
+cvo_status cvo_get_timing(cvo_handle h, cvo_timing *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CVO_H */

@@ -1,0 +1,1218 @@
+// cvo_api.hip -- host side of the library: the handle, its scratch arena,
+// preparation of the two cloud views, and the C ABI of include/cvo.h.
+//
+// Every call runs entirely on the GPU in the kernels of cvo_build.hip,
+// cvo_pairs.hip and cvo_reduce.hip; the host only validates arguments,
+// sizes buffers, launches, and copies small results back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/cvo.h"
+#include "cvo_launch.hpp"
+
+namespace cvo {
+bool pair_layout_supported(int sed, int lind);
+}
+
+using namespace cvo;
+
+namespace {
+
+struct CvoError : std::runtime_error {
+    cvo_status code;
+    CvoError(cvo_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIP_OK(expr)                                                                                    \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess)                                                                           \
+            throw CvoError(e_ == hipErrorOutOfMemory ? CVO_ERR_OUT_OF_MEMORY : CVO_ERR_DEVICE,          \
+                           std::string(#expr) + ": " + hipGetErrorString(e_));                          \
+    } while (0)
+
+inline void require(bool ok, const std::string &msg)
+{
+    if (!ok) throw CvoError(CVO_ERR_INVALID_ARGUMENT, msg);
+}
+
+constexpr double kLog2e = 1.4426950408889634;
+
+}  // namespace
+
+// ------------------------------------------------------------------ handle
+struct cvo_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    struct Buf {
+        void *p = nullptr;
+        size_t cap = 0;
+    };
+    std::map<std::string, Buf> bufs;
+    unsigned long long generation = 0;  // bumps whenever a buffer moves
+    void *pinned = nullptr;
+    size_t pinned_cap = 0;
+    cvo_tuning tuning{16, 1.0, 0.5, 0.5, 8, 0};
+    bool profiling = false;
+    cvo_timing timing{0, 0.0, 0, 0};
+    std::vector<hipEvent_t> ev_free;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+    std::map<std::string, cvo_tuning> tune_cache;
+    // captured batched graph
+    hipGraphExec_t graph = nullptr;
+    std::string graph_key;
+
+    void *get(const std::string &name, size_t bytes)
+    {
+        Buf &b = bufs[name];
+        if (bytes == 0) bytes = 16;
+        if (b.cap < bytes) {
+            if (b.p) HIP_OK(hipFree(b.p));
+            b.p = nullptr;
+            size_t cap = std::max(bytes, b.cap + b.cap / 2);
+            cap = (cap + 255) & ~size_t(255);
+            hipError_t e = hipMalloc(&b.p, cap);
+            if (e != hipSuccess) {
+                b.p = nullptr;
+                b.cap = 0;
+                throw CvoError(CVO_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(cap) +
+                                                          " bytes for " + name + " failed");
+            }
+            b.cap = cap;
+            ++generation;
+        }
+        return b.p;
+    }
+    template <class T> T *get_t(const std::string &name, size_t count)
+    {
+        return static_cast<T *>(get(name, count * sizeof(T)));
+    }
+    void *host(size_t bytes)
+    {
+        if (pinned_cap < bytes) {
+            if (pinned) HIP_OK(hipHostFree(pinned));
+            pinned = nullptr;
+            size_t cap = std::max(bytes, size_t(1) << 16);
+            HIP_OK(hipHostMalloc(&pinned, cap, hipHostMallocDefault));
+            pinned_cap = cap;
+        }
+        return pinned;
+    }
+    // copy host -> device through pinned memory and wait (setup-time only)
+    void upload(void *dst, const void *src, size_t bytes)
+    {
+        if (!bytes) return;
+        void *h = host(bytes);
+        std::memcpy(h, src, bytes);
+        HIP_OK(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, stream));
+        HIP_OK(hipStreamSynchronize(stream));
+    }
+    void download(void *dst, const void *src, size_t bytes)
+    {
+        if (!bytes) return;
+        void *h = host(bytes);
+        HIP_OK(hipMemcpyAsync(h, src, bytes, hipMemcpyDeviceToHost, stream));
+        HIP_OK(hipStreamSynchronize(stream));
+        std::memcpy(dst, h, bytes);
+    }
+    void check_launch(const char *what)
+    {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) throw CvoError(CVO_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    }
+    hipEvent_t event()
+    {
+        if (!ev_free.empty()) {
+            hipEvent_t e = ev_free.back();
+            ev_free.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        HIP_OK(hipEventCreate(&e));
+        return e;
+    }
+    void harvest_events()
+    {
+        for (auto &pr : ev_pending) {
+            float ms = 0.f;
+            HIP_OK(hipEventElapsedTime(&ms, pr.first, pr.second));
+            timing.pair_ms += ms;
+            timing.pair_launches += 1;
+            ev_free.push_back(pr.first);
+            ev_free.push_back(pr.second);
+        }
+        ev_pending.clear();
+    }
+    void release()
+    {
+        if (graph) hipGraphExecDestroy(graph);
+        graph = nullptr;
+        for (auto &kv : bufs)
+            if (kv.second.p) hipFree(kv.second.p);
+        bufs.clear();
+        if (pinned) hipHostFree(pinned);
+        pinned = nullptr;
+        for (auto &pr : ev_pending) {
+            hipEventDestroy(pr.first);
+            hipEventDestroy(pr.second);
+        }
+        for (auto e : ev_free) hipEventDestroy(e);
+        ev_free.clear();
+        ev_pending.clear();
+    }
+};
+
+namespace {
+
+// ------------------------------------------------------------------ validation
+void check_pose(const double *T)
+{
+    require(T != nullptr, "pose pointer is NULL");
+    for (int k = 0; k < 12; ++k) require(std::isfinite(T[k]), "pose has a non-finite entry");
+    double dev = 0.0;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += T[4 * k + r] * T[4 * k + c];
+            dev = std::max(dev, std::fabs(s - (r == c ? 1.0 : 0.0)));
+        }
+    const double det = T[0] * (T[5] * T[10] - T[6] * T[9]) - T[1] * (T[4] * T[10] - T[6] * T[8]) +
+                       T[2] * (T[4] * T[9] - T[5] * T[8]);
+    require(dev <= 1e-6 && det > 0.0, "pose rotation is not orthonormal with det +1 (tolerance 1e-6)");
+}
+
+int spec_dim(const cvo_feature_spec *sp)
+{
+    int D = 0;
+    for (int b = 0; b < sp->nblocks; ++b) D += sp->dim[b];
+    return D;
+}
+
+void check_spec(const cvo_feature_spec *sp)
+{
+    require(sp != nullptr, "feature spec is NULL");
+    require(sp->nblocks >= 0 && sp->nblocks <= CVO_MAX_BLOCKS, "nblocks out of range [0, 8]");
+    int nlin = 0;
+    for (int b = 0; b < sp->nblocks; ++b) {
+        require(sp->dim[b] > 0, "feature block dimension must be positive");
+        require(sp->kind[b] == CVO_SE || sp->kind[b] == CVO_LIN, "unknown feature block kind");
+        if (sp->kind[b] == CVO_SE)
+            require(std::isfinite(sp->ell[b]) && sp->ell[b] > 0.0 && std::isfinite(sp->sigma[b]) &&
+                        sp->sigma[b] > 0.0,
+                    "SE feature block needs finite ell > 0 and sigma > 0");
+        else
+            ++nlin;
+    }
+    if (nlin > 1) throw CvoError(CVO_ERR_UNSUPPORTED, "at most one LIN feature block is supported");
+    if (spec_dim(sp) > CVO_MAX_FEATURE_DIM) throw CvoError(CVO_ERR_UNSUPPORTED, "feature dimension above 64");
+}
+
+void check_cloud(const cvo_cloud *c, int D, const char *name)
+{
+    require(c != nullptr, std::string(name) + " cloud is NULL");
+    require(c->n >= 0 && c->n < (1LL << 30), std::string(name) + ": point count out of range");
+    if (c->n > 0) {
+        require(c->xyz != nullptr, std::string(name) + ": xyz is NULL");
+        if (D > 0) require(c->feat != nullptr, std::string(name) + ": feat is NULL but the spec has features");
+    }
+}
+
+void check_kp(const cvo_kernel_params *kp)
+{
+    require(kp != nullptr, "kernel params are NULL");
+    require(std::isfinite(kp->ell) && kp->ell > 0.0, "ell must be finite and > 0");
+    require(std::isfinite(kp->sigma) && kp->sigma > 0.0, "sigma must be finite and > 0");
+    require(!std::isnan(kp->kappa) && kp->kappa > 0.0, "kappa must be > 0 (+inf allowed)");
+}
+
+// ------------------------------------------------------------------ feature layout
+FeatLayout make_layout(const cvo_feature_spec *sp, double sigma)
+{
+    FeatLayout L;
+    std::memset(&L, 0, sizeof(L));
+    int sed = 0, lind = 0;
+    for (int b = 0; b < sp->nblocks; ++b) (sp->kind[b] == CVO_SE ? sed : lind) += sp->dim[b];
+    static const int S_opts[] = {0, 5, 8, 16, 32};
+    static const int L_opts[] = {0, 4, 19, 32, 64};
+    int bestS = -1, bestL = -1;
+    for (int S : S_opts)
+        for (int Lo : L_opts) {
+            if (S < sed || Lo < lind || !pair_layout_supported(S, Lo)) continue;
+            if (bestS < 0 || S + Lo < bestS + bestL) { bestS = S; bestL = Lo; }
+        }
+    if (bestS < 0) throw CvoError(CVO_ERR_UNSUPPORTED, "no compiled kernel for this feature layout");
+    L.sed = bestS;
+    L.lind = bestL;
+    L.d4 = (bestS + bestL + 3) & ~3;
+    L.src_dim = spec_dim(sp);
+    for (int k = 0; k < 64; ++k) { L.col[k] = -1; L.scale[k] = 0.f; L.gscale[k] = 0.0; }
+    double sig2 = sigma * sigma;
+    int dst = 0, src = 0;
+    for (int b = 0; b < sp->nblocks; ++b) {
+        if (sp->kind[b] == CVO_SE) {
+            const double f = std::sqrt(kLog2e / (2.0 * sp->ell[b] * sp->ell[b]));
+            for (int k = 0; k < sp->dim[b]; ++k) {
+                L.col[dst] = src + k;
+                L.scale[dst] = (float)f;
+                L.gscale[dst] = 1.0 / ((double)(float)f * sp->ell[b] * sp->ell[b]);
+                ++dst;
+            }
+            sig2 *= sp->sigma[b] * sp->sigma[b];
+        }
+        src += sp->dim[b];
+    }
+    dst = bestS;
+    src = 0;
+    for (int b = 0; b < sp->nblocks; ++b) {
+        if (sp->kind[b] == CVO_LIN)
+            for (int k = 0; k < sp->dim[b]; ++k) {
+                L.col[dst] = src + k;
+                L.scale[dst] = 1.f;
+                L.gscale[dst] = 1.0;
+                ++dst;
+            }
+        src += sp->dim[b];
+    }
+    L.sig2 = (float)sig2;
+    return L;
+}
+
+// ------------------------------------------------------------------ views
+struct GridView {
+    int B = 0;
+    std::vector<GridDesc> desc;
+    GridDesc *d_desc = nullptr;
+    float4 *pts = nullptr;
+    float *feat = nullptr;
+    int *perm = nullptr;
+    int *cell_start = nullptr;
+    long long ntot = 0;
+    std::vector<double> rc;
+};
+
+struct ClusterView {
+    int B = 0;
+    std::vector<ClusterDesc> desc;
+    ClusterDesc *d_desc = nullptr;
+    float4 *pts = nullptr;
+    float *feat = nullptr;
+    int *perm = nullptr;
+    int2 *clus = nullptr;
+    double4 *cgeo = nullptr;
+    int *cpair = nullptr;
+    int nclus = 0;
+    long long ntot = 0;
+    std::vector<double> rc;
+};
+
+int bits_for(unsigned long long v)
+{
+    int b = 0;
+    while ((1ULL << b) <= v && b < 63) ++b;
+    return b;
+}
+
+// bounding boxes and the non-finite check
+std::vector<float> cloud_boxes(cvo_context *ctx, const std::string &pre, const std::vector<CloudPtrs> &cl,
+                               CloudPtrs **d_clouds)
+{
+    const int B = (int)cl.size();
+    CloudPtrs *dc = ctx->get_t<CloudPtrs>(pre + ".clouds", B);
+    ctx->upload(dc, cl.data(), sizeof(CloudPtrs) * B);
+    float *d_box = ctx->get_t<float>(pre + ".box", 8 * B);
+    launch_bbox(dc, B, d_box, ctx->stream);
+    ctx->check_launch("bbox");
+    std::vector<float> box(8 * B);
+    ctx->download(box.data(), d_box, sizeof(float) * 8 * B);
+    for (int c = 0; c < B; ++c)
+        require(box[8 * c + 6] == 0.0f, "a cloud has non-finite coordinates");
+    *d_clouds = dc;
+    return box;
+}
+
+GridView build_grid(cvo_context *ctx, const std::string &pre, const std::vector<CloudPtrs> &cl,
+                    const std::vector<double> &rc, const FeatLayout &lay)
+{
+    GridView v;
+    const int B = (int)cl.size();
+    v.B = B;
+    v.rc = rc;
+    CloudPtrs *dc = nullptr;
+    std::vector<float> box = cloud_boxes(ctx, pre, cl, &dc);
+    const double cell_factor = ctx->tuning.cell_factor;
+    const long long cell_cap = 1LL << 23;
+    v.desc.resize(B);
+    long long cell_base = 0, pt_base = 0, max_cells = 0, nmax = 0;
+    std::vector<long long> bases(B);
+    for (int c = 0; c < B; ++c) {
+        GridDesc &g = v.desc[c];
+        std::memset(&g, 0, sizeof(g));
+        const long long n = cl[c].n;
+        if (n == 0) {
+            g.ox = g.oy = g.oz = 0.0;
+            g.h = 1.0;
+            g.nx = g.ny = g.nz = 1;
+        } else {
+            const double lo[3] = {box[8 * c], box[8 * c + 1], box[8 * c + 2]};
+            const double hi[3] = {box[8 * c + 3], box[8 * c + 4], box[8 * c + 5]};
+            double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-6});
+            double h = std::isfinite(rc[c]) ? cell_factor * rc[c] : ext * 1.01;
+            h = std::max(h, ext * 1e-6);
+            int nn[3];
+            for (;;) {
+                long long tot = 1;
+                for (int k = 0; k < 3; ++k) {
+                    nn[k] = (int)std::floor((hi[k] - lo[k]) / h) + 1;
+                    tot *= nn[k];
+                }
+                if (tot <= cell_cap && nn[0] < (1 << 30) / std::max(1, nn[1])) break;
+                h *= 1.25;
+            }
+            g.ox = lo[0];
+            g.oy = lo[1];
+            g.oz = lo[2];
+            g.h = h;
+            g.nx = nn[0];
+            g.ny = nn[1];
+            g.nz = nn[2];
+        }
+        g.cell_base = (int)cell_base;
+        g.pt_base = pt_base;
+        g.n = n;
+        bases[c] = pt_base;
+        const long long nc = (long long)g.nx * g.ny * g.nz;
+        max_cells = std::max(max_cells, nc);
+        cell_base += nc + 1;
+        pt_base += n;
+        nmax = std::max(nmax, n);
+    }
+    require(cell_base < (1LL << 31), "cell tables too large");
+    v.ntot = pt_base;
+    const int kbits = bits_for((unsigned long long)max_cells);  // max_cells itself must fit
+    const int cbits = bits_for((unsigned long long)(B > 1 ? B - 1 : 0));
+    require(kbits + cbits <= 62, "grid keys exceed 62 bits");
+    v.d_desc = ctx->get_t<GridDesc>(pre + ".desc", B);
+    ctx->upload(v.d_desc, v.desc.data(), sizeof(GridDesc) * B);
+    long long *d_base = ctx->get_t<long long>(pre + ".base", B);
+    ctx->upload(d_base, bases.data(), sizeof(long long) * B);
+
+    const long long ntot = std::max(v.ntot, 1LL);
+    unsigned long long *keys = ctx->get_t<unsigned long long>(pre + ".keys", ntot);
+    unsigned long long *ktmp = ctx->get_t<unsigned long long>(pre + ".ktmp", ntot);
+    int *vals = ctx->get_t<int>(pre + ".vals", ntot);
+    int *vtmp = ctx->get_t<int>(pre + ".vtmp", ntot);
+    const long long ntiles = (ntot + 4095) / 4096;
+    int *hist = ctx->get_t<int>(pre + ".hist", ntiles * 256);
+    int *bsum = ctx->get_t<int>(pre + ".bsum", (ntiles * 256 + 2047) / 2048 + 1);
+    v.pts = ctx->get_t<float4>(pre + ".pts", ntot);
+    v.feat = ctx->get_t<float>(pre + ".feat", ntot * std::max(lay.d4, 1));
+    v.perm = ctx->get_t<int>(pre + ".perm", ntot);
+    v.cell_start = ctx->get_t<int>(pre + ".cells", cell_base);
+    if (v.ntot > 0) {
+        launch_grid_keys(dc, v.d_desc, B, nmax, keys, vals, kbits, ctx->stream);
+        bool in_tmp = false;
+        launch_radix_sort(keys, vals, ktmp, vtmp, hist, bsum, v.ntot, kbits + cbits, ctx->stream, &in_tmp);
+        if (in_tmp) { std::swap(keys, ktmp); std::swap(vals, vtmp); }
+        launch_gather(keys, vals, v.ntot, kbits, dc, d_base, lay, v.pts, v.feat, v.perm, ctx->stream);
+    }
+    launch_cell_table(keys, v.ntot, v.d_desc, B, max_cells, kbits, v.cell_start, ctx->stream);
+    ctx->check_launch("grid build");
+    return v;
+}
+
+ClusterView build_clusters(cvo_context *ctx, const std::string &pre, const std::vector<CloudPtrs> &cl,
+                           const std::vector<double> &rc, const FeatLayout &lay)
+{
+    ClusterView v;
+    const int B = (int)cl.size();
+    v.B = B;
+    v.rc = rc;
+    CloudPtrs *dc = nullptr;
+    std::vector<float> box = cloud_boxes(ctx, pre, cl, &dc);
+    const int cbits = bits_for((unsigned long long)(B > 1 ? B - 1 : 0));
+    const int maxbits = std::min(19, (62 - cbits) / 3);
+    const int tpw = ctx->tuning.cluster_max;
+    std::vector<ClusterBuild> cb(B);
+    std::vector<int> lcap(B);
+    std::vector<long long> bases(B);
+    v.desc.resize(B);
+    long long pt_base = 0, nmax = 0;
+    for (int c = 0; c < B; ++c) {
+        const long long n = cl[c].n;
+        ClusterBuild &g = cb[c];
+        std::memset(&g, 0, sizeof(g));
+        double lo[3] = {0, 0, 0}, ext = 1.0;
+        if (n > 0) {
+            for (int k = 0; k < 3; ++k) lo[k] = box[8 * c + k];
+            ext = std::max({box[8 * c + 3] - lo[0], box[8 * c + 4] - lo[1], box[8 * c + 5] - lo[2], 1e-6});
+        }
+        const double cap = std::isfinite(rc[c]) ? ctx->tuning.cluster_factor * rc[c] : ext * 2.0;
+        int L = 4;
+        double q = cap / (double)(1 << L);
+        // quanta needed to cover the box must fit in maxbits per axis
+        if (ext / q + 1.0 > (double)(1 << maxbits)) {
+            q = ext / ((double)(1 << maxbits) - 2.0);
+            L = std::max(0, (int)std::floor(std::log2(std::max(cap / q, 1.0))));
+        }
+        L = std::min(L, maxbits);
+        g.ox = lo[0];
+        g.oy = lo[1];
+        g.oz = lo[2];
+        g.q = q;
+        g.pt_base = pt_base;
+        g.n = n;
+        lcap[c] = L;
+        bases[c] = pt_base;
+        ClusterDesc &d = v.desc[c];
+        d.clus_base = 0;
+        d.nclus = 0;
+        d.pt_base = (int)pt_base;
+        d.n = (int)n;
+        pt_base += n;
+        nmax = std::max(nmax, n);
+    }
+    v.ntot = pt_base;
+    const int bits = maxbits;
+    ClusterBuild *d_cb = ctx->get_t<ClusterBuild>(pre + ".cb", B);
+    ctx->upload(d_cb, cb.data(), sizeof(ClusterBuild) * B);
+    long long *d_base = ctx->get_t<long long>(pre + ".base", B);
+    ctx->upload(d_base, bases.data(), sizeof(long long) * B);
+    int *d_lcap = ctx->get_t<int>(pre + ".lcap", B);
+    ctx->upload(d_lcap, lcap.data(), sizeof(int) * B);
+    v.d_desc = ctx->get_t<ClusterDesc>(pre + ".desc", B);
+
+    const long long ntot = std::max(v.ntot, 1LL);
+    unsigned long long *keys = ctx->get_t<unsigned long long>(pre + ".keys", ntot);
+    unsigned long long *ktmp = ctx->get_t<unsigned long long>(pre + ".ktmp", ntot);
+    int *vals = ctx->get_t<int>(pre + ".vals", ntot);
+    int *vtmp = ctx->get_t<int>(pre + ".vtmp", ntot);
+    const long long ntiles = (ntot + 4095) / 4096;
+    int *hist = ctx->get_t<int>(pre + ".hist", std::max(ntiles * 256, ntot));
+    int *bsum = ctx->get_t<int>(pre + ".bsum", (std::max(ntiles * 256, ntot) + 2047) / 2048 + 1);
+    v.pts = ctx->get_t<float4>(pre + ".pts", ntot);
+    v.feat = ctx->get_t<float>(pre + ".feat", ntot * std::max(lay.d4, 1));
+    v.perm = ctx->get_t<int>(pre + ".perm", ntot);
+    v.clus = ctx->get_t<int2>(pre + ".clus", ntot);
+    v.cgeo = ctx->get_t<double4>(pre + ".cgeo", ntot);
+    v.cpair = ctx->get_t<int>(pre + ".cpair", ntot);
+    int *head = ctx->get_t<int>(pre + ".head", ntot);
+    int *hidx = ctx->get_t<int>(pre + ".hidx", ntot);
+    int2 *span = ctx->get_t<int2>(pre + ".span", ntot);
+    int *d_total = ctx->get_t<int>(pre + ".total", 1);
+    v.nclus = 0;
+    if (v.ntot > 0) {
+        launch_morton_keys(dc, d_cb, B, nmax, keys, vals, bits, ctx->stream);
+        bool in_tmp = false;
+        launch_radix_sort(keys, vals, ktmp, vtmp, hist, bsum, v.ntot, 3 * bits + cbits, ctx->stream, &in_tmp);
+        if (in_tmp) { std::swap(keys, ktmp); std::swap(vals, vtmp); }
+        launch_gather(keys, vals, v.ntot, 3 * bits, dc, d_base, lay, v.pts, v.feat, v.perm, ctx->stream);
+        launch_cluster_heads(keys, v.ntot, d_lcap, 3 * bits, tpw, head, span, ctx->stream);
+        launch_exclusive_scan(head, hidx, bsum, v.ntot, d_total, ctx->stream);
+        launch_cluster_emit(head, hidx, span, v.pts, keys, 3 * bits, v.ntot, v.clus, v.cgeo, v.cpair, ctx->stream);
+        ctx->check_launch("cluster build");
+        int total = 0;
+        ctx->download(&total, d_total, sizeof(int));
+        v.nclus = total;
+    }
+    ctx->upload(v.d_desc, v.desc.data(), sizeof(ClusterDesc) * B);
+    return v;
+}
+
+// ------------------------------------------------------------------ pair pass + reduce
+struct Moments {
+    double *W, *D, *G, *L;
+    float *S;
+    int *cnt;
+};
+
+Moments moments(cvo_context *ctx, const std::string &pre, long long n, int d4, bool backward)
+{
+    Moments m{};
+    n = std::max(n, 1LL);
+    m.W = ctx->get_t<double>(pre + ".W", n);
+    m.D = ctx->get_t<double>(pre + ".D", 3 * n);
+    m.cnt = ctx->get_t<int>(pre + ".cnt", n);
+    if (backward) {
+        m.G = ctx->get_t<double>(pre + ".G", n * std::max(d4, 1));
+        m.L = ctx->get_t<double>(pre + ".L", n);
+        m.S = nullptr;
+    } else {
+        m.S = ctx->get_t<float>(pre + ".S", 6 * n);
+        m.G = m.L = nullptr;
+    }
+    return m;
+}
+
+PairPassArgs pass_args(const ClusterView &q, const GridView &r, const PairState *st, int inverse, float sig2,
+                       double kappa, const Moments &m)
+{
+    PairPassArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.qpts = q.pts;
+    a.qfeat = q.feat;
+    a.clus = q.clus;
+    a.cgeo = q.cgeo;
+    a.cpair = q.cpair;
+    a.nclus = q.nclus;
+    a.rpts = r.pts;
+    a.rfeat = r.feat;
+    a.cell_start = r.cell_start;
+    a.grids = r.d_desc;
+    a.state = st;
+    a.pose_is_inverse = inverse;
+    a.sig2 = sig2;
+    a.kappa = kappa;
+    a.oW = m.W;
+    a.oD = m.D;
+    a.oS = m.S;
+    a.oCnt = m.cnt;
+    a.oG = m.G;
+    a.oL = m.L;
+    return a;
+}
+
+void run_pair_pass(cvo_context *ctx, const PairPassArgs &a, const FeatLayout &lay, int mode)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ctx->profiling) {
+        e0 = ctx->event();
+        e1 = ctx->event();
+        HIP_OK(hipEventRecord(e0, ctx->stream));
+    }
+    if (!launch_pair_pass(a, lay, mode, ctx->stream))
+        throw CvoError(CVO_ERR_UNSUPPORTED, "no compiled pair kernel for the feature layout");
+    ctx->check_launch("pair pass");
+    if (ctx->profiling) {
+        HIP_OK(hipEventRecord(e1, ctx->stream));
+        ctx->ev_pending.push_back({e0, e1});
+    }
+    ctx->timing.evaluations += 1;
+}
+
+int reduce_blocks(const std::vector<ClusterDesc> &cd)
+{
+    long long mx = 1;
+    for (auto &d : cd) mx = std::max(mx, (long long)d.n);
+    long long nb = (mx + 4 * kRedThreads - 1) / (4 * kRedThreads);
+    return (int)std::min(std::max(nb, 1LL), 64LL);
+}
+
+PairState init_state(const double *T, double ell)
+{
+    PairState s;
+    std::memset(&s, 0, sizeof(s));
+    std::memcpy(s.T, T, sizeof(double) * 12);
+    for (int r = 0; r < 3; ++r) {
+        for (int k = 0; k < 3; ++k) s.Tinv[4 * r + k] = T[4 * k + r];
+        s.Tinv[4 * r + 3] = -(T[r] * T[3] + T[4 + r] * T[7] + T[8 + r] * T[11]);
+    }
+    s.ell = ell;
+    s.i_prev = NAN;
+    s.status = ST_RUNNING;
+    s.done = 0;
+    return s;
+}
+
+// Everything a forward evaluation or an ascent needs for B pairs.
+struct Problem {
+    FeatLayout lay;
+    GridView grid;       // X clouds, reference role
+    ClusterView clus;    // Z clouds, query role
+    Moments mom;
+    PairState *d_state = nullptr;
+    AlignConst *d_ac = nullptr;
+    double *partials = nullptr;
+    unsigned int *counters = nullptr;
+    int nblk = 1;
+    double kappa = 3.0;
+    float sig2 = 1.f;
+};
+
+void build_views(cvo_context *ctx, Problem &p, const std::vector<CloudPtrs> &X, const std::vector<CloudPtrs> &Z,
+                 const std::vector<double> &ell)
+{
+    std::vector<double> rc(ell.size());
+    for (size_t k = 0; k < ell.size(); ++k) rc[k] = p.kappa * ell[k];
+    p.grid = build_grid(ctx, "fx", X, rc, p.lay);
+    p.clus = build_clusters(ctx, "fz", Z, rc, p.lay);
+    p.mom = moments(ctx, "fm", p.clus.ntot, p.lay.d4, false);
+}
+
+void setup_problem(cvo_context *ctx, Problem &p, const std::vector<CloudPtrs> &X, const std::vector<CloudPtrs> &Z,
+                   const std::vector<PairState> &st, const std::vector<AlignConst> &ac)
+{
+    const int B = (int)X.size();
+    std::vector<double> ell(B);
+    for (int b = 0; b < B; ++b) ell[b] = st[b].ell;
+    build_views(ctx, p, X, Z, ell);
+    p.d_state = ctx->get_t<PairState>("state", B);
+    ctx->upload(p.d_state, st.data(), sizeof(PairState) * B);
+    p.d_ac = ctx->get_t<AlignConst>("aconst", B);
+    ctx->upload(p.d_ac, ac.data(), sizeof(AlignConst) * B);
+    p.nblk = reduce_blocks(p.clus.desc);
+    p.partials = ctx->get_t<double>("partials", (size_t)B * p.nblk * kRedVals);
+    p.counters = ctx->get_t<unsigned int>("counters", B);
+    HIP_OK(hipMemsetAsync(p.counters, 0, sizeof(unsigned int) * B, ctx->stream));
+}
+
+void enqueue_iteration(cvo_context *ctx, Problem &p, int mode, double *trace, long long trace_rows, bool timed)
+{
+    PairPassArgs a = pass_args(p.clus, p.grid, p.d_state, 0, p.sig2, p.kappa, p.mom);
+    if (timed) run_pair_pass(ctx, a, p.lay, 0);
+    else {
+        if (!launch_pair_pass(a, p.lay, 0, ctx->stream))
+            throw CvoError(CVO_ERR_UNSUPPORTED, "no compiled pair kernel for the feature layout");
+        ctx->timing.evaluations += 1;
+    }
+    ReduceArgs r;
+    std::memset(&r, 0, sizeof(r));
+    r.qpts = p.clus.pts;
+    r.cdesc = p.clus.d_desc;
+    r.W = p.mom.W;
+    r.D = p.mom.D;
+    r.S = p.mom.S;
+    r.cnt = p.mom.cnt;
+    r.state = p.d_state;
+    r.ac = p.d_ac;
+    r.partials = p.partials;
+    r.counters = p.counters;
+    r.trace = trace;
+    r.trace_rows = trace_rows;
+    r.nblk = p.nblk;
+    r.mode = mode;
+    launch_reduce(r, p.grid.B, ctx->stream);
+    ctx->check_launch("reduce");
+}
+
+CloudPtrs to_ptrs(const cvo_cloud *c)
+{
+    CloudPtrs p;
+    p.xyz = c->xyz;
+    p.feat = c->feat;
+    p.n = c->n;
+    return p;
+}
+
+AlignConst const_for(const cvo_align_params *ap, long long N, long long M)
+{
+    AlignConst a;
+    std::memset(&a, 0, sizeof(a));
+    if (ap) {
+        a.ell_min = ap->ell_min;
+        a.decay = ap->decay;
+        a.ind_rel_tol = ap->ind_rel_tol;
+        a.eps_rot = ap->eps_rot;
+        a.eps_trans = ap->eps_trans;
+        a.step_lambda = ap->step_lambda;
+        a.max_iter = ap->max_iter;
+        a.fixed_iters = ap->fixed_iters;
+    } else {
+        a.max_iter = 1;
+        a.step_lambda = 1.0;
+    }
+    a.sqrt_nm = std::sqrt((double)N * (double)M);
+    return a;
+}
+
+void check_align_params(const cvo_align_params *ap)
+{
+    require(ap != nullptr, "align params are NULL");
+    require(std::isfinite(ap->ell_init) && ap->ell_init > 0.0, "ell_init must be finite and > 0");
+    require(std::isfinite(ap->ell_min) && ap->ell_min > 0.0, "ell_min must be finite and > 0");
+    require(ap->decay > 0.0 && ap->decay < 1.0, "decay must lie in (0, 1)");
+    require(ap->ind_rel_tol >= 0.0, "ind_rel_tol must be >= 0");
+    require(ap->eps_rot >= 0.0 && ap->eps_trans >= 0.0, "eps must be >= 0");
+    require(std::isfinite(ap->step_lambda) && ap->step_lambda > 0.0, "step_lambda must be > 0");
+    require(std::isfinite(ap->sigma) && ap->sigma > 0.0, "sigma must be > 0");
+    require(!std::isnan(ap->kappa) && ap->kappa > 0.0, "kappa must be > 0");
+    require(ap->max_iter >= 1, "max_iter must be >= 1");
+}
+
+// single forward evaluation
+void evaluate_one(cvo_context *ctx, const cvo_cloud *X, const cvo_cloud *Z, const cvo_feature_spec *spec,
+                  const cvo_kernel_params *kp, const double *T, PairState *out)
+{
+    check_spec(spec);
+    const int D = spec_dim(spec);
+    check_cloud(X, D, "X");
+    check_cloud(Z, D, "Z");
+    check_kp(kp);
+    check_pose(T);
+    PairState s0 = init_state(T, kp->ell);
+    if (X->n == 0 || Z->n == 0) {
+        *out = s0;
+        return;
+    }
+    Problem p;
+    p.kappa = kp->kappa;
+    p.lay = make_layout(spec, kp->sigma);
+    p.sig2 = p.lay.sig2;
+    AlignConst ac = const_for(nullptr, X->n, Z->n);
+    setup_problem(ctx, p, {to_ptrs(X)}, {to_ptrs(Z)}, {s0}, {ac});
+    enqueue_iteration(ctx, p, 0, nullptr, 0, ctx->profiling);
+    ctx->download(out, p.d_state, sizeof(PairState));
+    if (ctx->profiling) {
+        ctx->harvest_events();
+        ctx->timing.pair_count += (long long)out->n_pairs;
+    }
+}
+
+cvo_status fail(cvo_context *ctx, const CvoError &e)
+{
+    if (ctx) ctx->err = e.what();
+    return e.code;
+}
+
+template <class F> cvo_status guarded(cvo_context *ctx, F &&f)
+{
+    if (!ctx) return CVO_ERR_INVALID_ARGUMENT;
+    ctx->err.clear();
+    try {
+        HIP_OK(hipSetDevice(ctx->device));
+        f();
+        return CVO_OK;
+    } catch (const CvoError &e) {
+        return fail(ctx, e);
+    } catch (const std::exception &e) {
+        ctx->err = e.what();
+        return CVO_ERR_DEVICE;
+    }
+}
+
+// ------------------------------------------------------------------ ascent driver
+void align_many(cvo_context *ctx, const std::vector<CloudPtrs> &X, const std::vector<CloudPtrs> &Z,
+                const cvo_feature_spec *spec, const std::vector<cvo_align_params> &prm,
+                const std::vector<const double *> &T0, std::vector<PairState> &final_state, double *trace_host,
+                bool use_graph)
+{
+    const int B = (int)X.size();
+    Problem p;
+    p.kappa = prm[0].kappa;
+    p.lay = make_layout(spec, prm[0].sigma);
+    p.sig2 = p.lay.sig2;
+    std::vector<PairState> st(B);
+    std::vector<AlignConst> ac(B);
+    long long trace_rows = 0;
+    for (int b = 0; b < B; ++b) {
+        st[b] = init_state(T0[b], prm[b].ell_init);
+        ac[b] = const_for(&prm[b], X[b].n, Z[b].n);
+        if (X[b].n == 0 || Z[b].n == 0) {
+            st[b].status = ST_NO_OVERLAP;
+            st[b].done = 1;
+        }
+        trace_rows = std::max(trace_rows, (long long)prm[b].max_iter);
+    }
+    double *d_trace = trace_host ? ctx->get_t<double>("trace", (size_t)B * trace_rows * kTraceLen) : nullptr;
+    setup_problem(ctx, p, X, Z, st, ac);
+    const int U = std::max(1, std::min(64, (int)ctx->tuning.unroll));
+    const bool cut = std::isfinite(p.kappa);
+    std::vector<PairState> now(B);
+    PairState *h_state = static_cast<PairState *>(ctx->host(sizeof(PairState) * B));
+    (void)h_state;
+    for (;;) {
+        if (use_graph) {
+            const std::string key = std::to_string(ctx->generation) + ":" + std::to_string(p.clus.nclus) + ":" +
+                                    std::to_string(B) + ":" + std::to_string(U);
+            if (!ctx->graph || ctx->graph_key != key) {
+                if (ctx->graph) HIP_OK(hipGraphExecDestroy(ctx->graph));
+                ctx->graph = nullptr;
+                hipGraph_t g;
+                HIP_OK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+                for (int u = 0; u < U; ++u) enqueue_iteration(ctx, p, 1, d_trace, trace_rows, false);
+                HIP_OK(hipStreamEndCapture(ctx->stream, &g));
+                HIP_OK(hipGraphInstantiate(&ctx->graph, g, nullptr, nullptr, 0));
+                HIP_OK(hipGraphDestroy(g));
+                ctx->graph_key = key;
+            }
+            HIP_OK(hipGraphLaunch(ctx->graph, ctx->stream));
+        } else {
+            for (int u = 0; u < U; ++u) enqueue_iteration(ctx, p, 1, d_trace, trace_rows, ctx->profiling);
+        }
+        ctx->download(now.data(), p.d_state, sizeof(PairState) * B);
+        if (ctx->profiling) ctx->harvest_events();
+        bool all_done = true, rebuild = false;
+        for (int b = 0; b < B; ++b) {
+            if (!now[b].done) {
+                all_done = false;
+                if (cut && p.kappa * now[b].ell < ctx->tuning.rebuild_ratio * p.grid.rc[b]) rebuild = true;
+            }
+        }
+        if (all_done) break;
+        if (rebuild) {
+            std::vector<double> ell(B);
+            for (int b = 0; b < B; ++b) ell[b] = now[b].ell;
+            build_views(ctx, p, X, Z, ell);
+        }
+    }
+    final_state = now;
+    if (ctx->profiling)
+        for (int b = 0; b < B; ++b) ctx->timing.pair_count += (long long)now[b].total_pairs;
+    if (trace_host && d_trace)
+        ctx->download(trace_host, d_trace, sizeof(double) * (size_t)B * trace_rows * kTraceLen);
+}
+
+void fill_report(const PairState &s, cvo_align_report *r)
+{
+    std::memset(r, 0, sizeof(*r));
+    r->iterations = s.it;
+    r->final_ell = s.ell;
+    r->F = s.F;
+    r->i_theta = s.i_theta;
+    r->n_pairs = (int64_t)s.n_pairs;
+    r->status = s.status == ST_RUNNING ? CVO_MAX_ITER : s.status;
+    r->total_pairs = (int64_t)s.total_pairs;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+cvo_status cvo_create(cvo_handle *out, int device, void *stream)
+{
+    if (!out) return CVO_ERR_INVALID_ARGUMENT;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return CVO_ERR_INVALID_ARGUMENT;
+    cvo_context *ctx = new (std::nothrow) cvo_context();
+    if (!ctx) return CVO_ERR_OUT_OF_MEMORY;
+    ctx->device = device;
+    ctx->stream = static_cast<hipStream_t>(stream);
+    if (hipSetDevice(device) != hipSuccess) {
+        delete ctx;
+        return CVO_ERR_DEVICE;
+    }
+    *out = ctx;
+    return CVO_OK;
+}
+
+void cvo_destroy(cvo_handle h)
+{
+    if (!h) return;
+    hipSetDevice(h->device);
+    if (h->stream) hipStreamSynchronize(h->stream);
+    h->release();
+    delete h;
+}
+
+cvo_status cvo_set_stream(cvo_handle h, void *stream)
+{
+    if (!h) return CVO_ERR_INVALID_ARGUMENT;
+    h->stream = static_cast<hipStream_t>(stream);
+    return CVO_OK;
+}
+
+const char *cvo_last_error(cvo_handle h) { return h ? h->err.c_str() : "NULL handle"; }
+
+cvo_status cvo_inner_product(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z, const cvo_feature_spec *spec,
+                             const cvo_kernel_params *kp, const double T[12], double *F, int64_t *n_pairs)
+{
+    return guarded(h, [&] {
+        require(F != nullptr, "F output is NULL");
+        PairState s;
+        evaluate_one(h, X, Z, spec, kp, T, &s);
+        *F = s.F;
+        if (n_pairs) *n_pairs = (int64_t)s.n_pairs;
+    });
+}
+
+cvo_status cvo_gradient(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z, const cvo_feature_spec *spec,
+                        const cvo_kernel_params *kp, const double T[12], double *F, double grad[6],
+                        int64_t *n_pairs)
+{
+    return guarded(h, [&] {
+        require(grad != nullptr, "grad output is NULL");
+        PairState s;
+        evaluate_one(h, X, Z, spec, kp, T, &s);
+        if (F) *F = s.F;
+        for (int k = 0; k < 6; ++k) grad[k] = s.grad[k];
+        if (n_pairs) *n_pairs = (int64_t)s.n_pairs;
+    });
+}
+
+cvo_status cvo_evaluate(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z, const cvo_feature_spec *spec,
+                        const cvo_kernel_params *kp, const double T[12], cvo_eval *out)
+{
+    return guarded(h, [&] {
+        require(out != nullptr, "output is NULL");
+        PairState s;
+        evaluate_one(h, X, Z, spec, kp, T, &s);
+        out->F = s.F;
+        for (int k = 0; k < 6; ++k) out->grad[k] = s.grad[k];
+        out->curv = s.curv;
+        out->dF_dell = s.dF_dell;
+        out->r_max = s.r_max;
+        out->i_theta = s.i_theta;
+        out->n_pairs = (int64_t)s.n_pairs;
+    });
+}
+
+cvo_status cvo_metric(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z, const cvo_feature_spec *spec,
+                      const cvo_kernel_params *kp, const double T[12], double *i_theta)
+{
+    return guarded(h, [&] {
+        require(i_theta != nullptr, "output is NULL");
+        PairState s;
+        evaluate_one(h, X, Z, spec, kp, T, &s);
+        *i_theta = (X->n > 0 && Z->n > 0) ? s.i_theta : 0.0;
+    });
+}
+
+cvo_status cvo_align(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z, const cvo_feature_spec *spec,
+                     const cvo_align_params *ap, const double T_init[12], double T_out[12],
+                     cvo_align_report *report, double *trace)
+{
+    return guarded(h, [&] {
+        check_spec(spec);
+        const int D = spec_dim(spec);
+        check_cloud(X, D, "X");
+        check_cloud(Z, D, "Z");
+        check_align_params(ap);
+        check_pose(T_init);
+        require(T_out != nullptr && report != nullptr, "T_out / report is NULL");
+        if (X->n == 0 || Z->n == 0) {
+            std::memcpy(T_out, T_init, sizeof(double) * 12);
+            PairState s = init_state(T_init, ap->ell_init);
+            s.status = ST_NO_OVERLAP;
+            fill_report(s, report);
+            return;
+        }
+        std::vector<PairState> fin;
+        align_many(h, {to_ptrs(X)}, {to_ptrs(Z)}, spec, {*ap}, {T_init}, fin, trace, false);
+        std::memcpy(T_out, fin[0].T, sizeof(double) * 12);
+        fill_report(fin[0], report);
+    });
+}
+
+cvo_status cvo_align_batched(cvo_handle h, int32_t B, const cvo_cloud *X, const cvo_cloud *Z,
+                             const cvo_feature_spec *spec, const cvo_align_params *params, int32_t nparams,
+                             const double *T_init, double *T_out, cvo_align_report *reports)
+{
+    return guarded(h, [&] {
+        require(B >= 1, "B must be >= 1");
+        require(X && Z && params && T_init && T_out && reports, "NULL argument");
+        require(nparams == 1 || nparams == B, "nparams must be 1 or B");
+        check_spec(spec);
+        const int D = spec_dim(spec);
+        std::vector<CloudPtrs> xs(B), zs(B);
+        std::vector<cvo_align_params> prm(B);
+        std::vector<const double *> T0(B);
+        for (int b = 0; b < B; ++b) {
+            check_cloud(&X[b], D, "X");
+            check_cloud(&Z[b], D, "Z");
+            prm[b] = params[nparams == 1 ? 0 : b];
+            check_align_params(&prm[b]);
+            require(prm[b].kappa == prm[0].kappa && prm[b].sigma == prm[0].sigma,
+                    "kappa and sigma must be shared by all pairs of a batch");
+            T0[b] = T_init + 12 * b;
+            check_pose(T0[b]);
+            xs[b] = to_ptrs(&X[b]);
+            zs[b] = to_ptrs(&Z[b]);
+        }
+        std::vector<PairState> fin;
+        align_many(h, xs, zs, spec, prm, T0, fin, nullptr, true);
+        for (int b = 0; b < B; ++b) {
+            std::memcpy(T_out + 12 * b, fin[b].T, sizeof(double) * 12);
+            fill_report(fin[b], &reports[b]);
+        }
+    });
+}
+
+cvo_status cvo_inner_product_backward(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,
+                                      const cvo_feature_spec *spec, const cvo_kernel_params *kp, const double T[12],
+                                      double gF, float *dX, float *dZ, float *dU, float *dV, double *dEll)
+{
+    return guarded(h, [&] {
+        check_spec(spec);
+        const int D = spec_dim(spec);
+        check_cloud(X, D, "X");
+        check_cloud(Z, D, "Z");
+        check_kp(kp);
+        check_pose(T);
+        require(std::isfinite(gF), "gF must be finite");
+        if (D == 0) { dU = nullptr; dV = nullptr; }
+        const long long N = X->n, M = Z->n;
+        if (N == 0 || M == 0) {
+            if (dX && N) HIP_OK(hipMemsetAsync(dX, 0, sizeof(float) * 3 * N, h->stream));
+            if (dU && N) HIP_OK(hipMemsetAsync(dU, 0, sizeof(float) * D * N, h->stream));
+            if (dZ && M) HIP_OK(hipMemsetAsync(dZ, 0, sizeof(float) * 3 * M, h->stream));
+            if (dV && M) HIP_OK(hipMemsetAsync(dV, 0, sizeof(float) * D * M, h->stream));
+            HIP_OK(hipStreamSynchronize(h->stream));
+            if (dEll) *dEll = 0.0;
+            return;
+        }
+        const FeatLayout lay = make_layout(spec, kp->sigma);
+        const double rc = kp->kappa * kp->ell;
+        PairState s0 = init_state(T, kp->ell);
+        PairState *d_state = h->get_t<PairState>("bstate", 1);
+        h->upload(d_state, &s0, sizeof(PairState));
+        // target side: queries Z (pose T) against the X grid
+        if (dZ || dV || dEll) {
+            GridView gx = build_grid(h, "fx", {to_ptrs(X)}, {rc}, lay);
+            ClusterView cz = build_clusters(h, "fz", {to_ptrs(Z)}, {rc}, lay);
+            Moments m = moments(h, "bm", cz.ntot, lay.d4, true);
+            PairPassArgs a = pass_args(cz, gx, d_state, 0, lay.sig2, kp->kappa, m);
+            run_pair_pass(h, a, lay, 1);
+            BackwardArgs ba;
+            std::memset(&ba, 0, sizeof(ba));
+            ba.qperm = cz.perm;
+            ba.D = m.D;
+            ba.G = m.G;
+            ba.state = d_state;
+            ba.pose_is_inverse = 0;
+            ba.lay = lay;
+            ba.gF = gF;
+            ba.dxyz = dZ;
+            ba.dfeat = dV;
+            ba.n = M;
+            launch_backward_finish(ba, h->stream);
+            if (dEll) {
+                double *d_sum = h->get_t<double>("bsum", 1);
+                launch_sum_doubles(m.L, M, d_sum, h->stream);
+                double sl = 0.0;
+                h->download(&sl, d_sum, sizeof(double));
+                const double ascale = kLog2e / (2.0 * kp->ell * kp->ell);
+                *dEll = gF * sl / (ascale * kp->ell * kp->ell * kp->ell);
+            }
+            h->check_launch("backward (target side)");
+        }
+        // source side: queries X (pose T^-1) against the Z grid
+        if (dX || dU) {
+            GridView gz = build_grid(h, "rz", {to_ptrs(Z)}, {rc}, lay);
+            ClusterView cx = build_clusters(h, "rx", {to_ptrs(X)}, {rc}, lay);
+            Moments m = moments(h, "bm2", cx.ntot, lay.d4, true);
+            PairPassArgs a = pass_args(cx, gz, d_state, 1, lay.sig2, kp->kappa, m);
+            run_pair_pass(h, a, lay, 1);
+            BackwardArgs ba;
+            std::memset(&ba, 0, sizeof(ba));
+            ba.qperm = cx.perm;
+            ba.D = m.D;
+            ba.G = m.G;
+            ba.state = d_state;
+            ba.pose_is_inverse = 1;
+            ba.lay = lay;
+            ba.gF = gF;
+            ba.dxyz = dX;
+            ba.dfeat = dU;
+            ba.n = N;
+            launch_backward_finish(ba, h->stream);
+            h->check_launch("backward (source side)");
+        }
+        HIP_OK(hipStreamSynchronize(h->stream));
+        if (h->profiling) h->harvest_events();
+    });
+}
+
+cvo_status cvo_get_tuning(cvo_handle h, cvo_tuning *out)
+{
+    if (!h || !out) return CVO_ERR_INVALID_ARGUMENT;
+    *out = h->tuning;
+    return CVO_OK;
+}
+
+cvo_status cvo_set_tuning(cvo_handle h, const cvo_tuning *in)
+{
+    return guarded(h, [&] {
+        require(in != nullptr, "tuning is NULL");
+        require(in->cluster_max == 8 || in->cluster_max == 16 || in->cluster_max == 32 || in->cluster_max == 64,
+                "cluster_max must be 8, 16, 32 or 64");
+        require(in->cell_factor >= 0.25 && in->cell_factor <= 4.0, "cell_factor out of [0.25, 4]");
+        require(in->cluster_factor >= 0.05 && in->cluster_factor <= 2.0, "cluster_factor out of [0.05, 2]");
+        require(in->rebuild_ratio > 0.0 && in->rebuild_ratio <= 1.0, "rebuild_ratio out of (0, 1]");
+        require(in->unroll >= 1 && in->unroll <= 64, "unroll out of [1, 64]");
+        h->tuning = *in;
+    });
+}
+
+cvo_status cvo_set_profiling(cvo_handle h, int32_t enable)
+{
+    if (!h) return CVO_ERR_INVALID_ARGUMENT;
+    h->profiling = enable != 0;
+    if (h->profiling) h->timing = cvo_timing{0, 0.0, 0, 0};
+    return CVO_OK;
+}
+
+cvo_status cvo_get_timing(cvo_handle h, cvo_timing *out)
+{
+    if (!h || !out) return CVO_ERR_INVALID_ARGUMENT;
+    *out = h->timing;
+    return CVO_OK;
+}
+
+cvo_status cvo_autotune(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z, const cvo_feature_spec *spec,
+                        const cvo_kernel_params *kp, const double T[12], cvo_tuning *chosen)
+{
+    return guarded(h, [&] {
+        check_spec(spec);
+        const int D = spec_dim(spec);
+        check_cloud(X, D, "X");
+        check_cloud(Z, D, "Z");
+        check_kp(kp);
+        check_pose(T);
+        auto bucket = [](long long n) { return bits_for((unsigned long long)std::max(n, 1LL)); };
+        const std::string key = std::to_string(bucket(X->n)) + "/" + std::to_string(bucket(Z->n)) + "/" +
+                                std::to_string(D) + "/" + std::to_string((int)std::floor(std::log2(kp->ell) * 2));
+        auto it = h->tune_cache.find(key);
+        if (it != h->tune_cache.end()) {
+            h->tuning = it->second;
+            if (chosen) *chosen = it->second;
+            return;
+        }
+        const cvo_tuning base = h->tuning;
+        cvo_tuning best = base;
+        float best_ms = INFINITY;
+        const bool prof = h->profiling;
+        const cvo_timing saved = h->timing;
+        for (int cm : {8, 16, 32, 64})
+            for (double cf : {0.5, 0.75, 1.0}) {
+                cvo_tuning t = base;
+                t.cluster_max = cm;
+                t.cell_factor = cf;
+                h->tuning = t;
+                Problem p;
+                p.kappa = kp->kappa;
+                p.lay = make_layout(spec, kp->sigma);
+                p.sig2 = p.lay.sig2;
+                PairState s0 = init_state(T, kp->ell);
+                AlignConst ac = const_for(nullptr, X->n, Z->n);
+                setup_problem(h, p, {to_ptrs(X)}, {to_ptrs(Z)}, {s0}, {ac});
+                PairPassArgs a = pass_args(p.clus, p.grid, p.d_state, 0, p.sig2, p.kappa, p.mom);
+                hipEvent_t e0 = h->event(), e1 = h->event();
+                std::vector<float> ms;
+                for (int rep = 0; rep < 4; ++rep) {
+                    HIP_OK(hipEventRecord(e0, h->stream));
+                    if (!launch_pair_pass(a, p.lay, 0, h->stream))
+                        throw CvoError(CVO_ERR_UNSUPPORTED, "no compiled pair kernel for the feature layout");
+                    HIP_OK(hipEventRecord(e1, h->stream));
+                    HIP_OK(hipEventSynchronize(e1));
+                    float v = 0.f;
+                    HIP_OK(hipEventElapsedTime(&v, e0, e1));
+                    if (rep > 0) ms.push_back(v);
+                }
+                h->ev_free.push_back(e0);
+                h->ev_free.push_back(e1);
+                std::sort(ms.begin(), ms.end());
+                const float med = ms[ms.size() / 2];
+                if (med < best_ms) {
+                    best_ms = med;
+                    best = t;
+                }
+            }
+        h->profiling = prof;
+        h->timing = saved;
+        h->tuning = best;
+        h->tune_cache[key] = best;
+        if (chosen) *chosen = best;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+// cvo_internal.hpp -- shared host/device definitions of the gfx950 CVO library.
+//
+// Data layout in HBM (all arrays live in the handle's arena):
+//   A cloud is prepared in one of two views, both holding sorted float4 copies
+//   of the raw float32 coordinates (w unused) and sorted, padded feature rows
+//   (stride D4 floats; SE columns pre-multiplied by sqrt(log2(e) / (2 ell_b^2))
+//   so one exp2 of a plain sum of squares gives every SE factor, LIN columns
+//   unscaled; padding columns are zero):
+//     grid view    (reference side of a pair pass): points sorted by the
+//                  row-major index of a uniform cell grid; a dense table
+//                  cell_start[k] = first sorted index with cell >= k, so a
+//                  run of cells along x is one contiguous index range.
+//     cluster view (query side): points sorted by a Morton code; a cluster is
+//                  an aligned octree block holding at most cluster_max points,
+//                  with its centre and radius in the cloud's own frame.  A
+//                  rigid motion keeps clusters compact, so they are built once
+//                  per lengthscale band, never per iteration.
+//   Several clouds are prepared together by prefixing every sort key with the
+//   cloud index; the plain path is the batch of one.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cvo {
+
+constexpr int kWave = 64;
+constexpr int kWavesPerBlock = 4;
+constexpr int kQueueCap = 128;   // LDS candidate queue per wave
+constexpr int kQueueFlush = 64;  // process the queue once it holds this many
+constexpr int kTraceLen = 8;
+constexpr int kRedVals = 32;     // values reduced per pair by the reduction kernel
+constexpr int kRedThreads = 256;
+
+enum Status { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAX_ITER = 2, ST_NO_OVERLAP = 3, ST_STATIONARY = 4 };
+
+// Per-pair registration state, resident on the device for the whole ascent.
+struct alignas(16) PairState {
+    double T[12];        // current pose [R|t], maps the Z frame into the X frame
+    double Tinv[12];     // inverse pose (used by the source-side backward pass)
+    double ell;          // current lengthscale
+    double i_prev;       // indicator at the previous iteration (NaN: none)
+    double F, i_theta, curv, tau, gnorm, r_max, dF_dell;
+    double grad[6];
+    double n_pairs;      // |P| of the last evaluation (exact integer in a double)
+    double total_pairs;  // sum of |P| over the registration
+    long long it;        // steps taken
+    int status;          // Status
+    int done;            // nonzero: later launches skip this pair
+};
+
+// Per-pair constants of the ascent.
+struct alignas(16) AlignConst {
+    double ell_min, decay, ind_rel_tol, eps_rot, eps_trans, step_lambda;
+    double sqrt_nm;      // sqrt(|X| |Z|)
+    long long max_iter;
+    int fixed_iters;
+    int pad;
+};
+
+// Uniform grid of one cloud (reference role).
+struct alignas(16) GridDesc {
+    double ox, oy, oz;   // origin (cell (0,0,0) starts here)
+    double h;            // cell edge (m)
+    int nx, ny, nz;
+    int cell_base;       // offset of this cloud's table in cell_start
+    long long pt_base;   // sorted points of this cloud: [pt_base, pt_base + n)
+    long long n;
+};
+
+// Clusters of one cloud (query role).
+struct alignas(16) ClusterDesc {
+    int clus_base, nclus;  // clusters [clus_base, clus_base + nclus)
+    int pt_base, n;        // sorted points [pt_base, pt_base + n)
+};
+
+// Feature layout after combining the spec's blocks: all SE columns first
+// (pre-scaled), then at most one LIN block.
+struct FeatLayout {
+    int sed, lind;     // SE columns, LIN columns of the kernel variant (padded)
+    int d4;            // row stride (multiple of 4, >= sed + lind)
+    int src_dim;       // D of the caller's rows
+    int col[64];       // destination column -> source column (-1: zero padding)
+    float scale[64];   // destination column scale (SE: sqrt(log2(e) / (2 ell_b^2)))
+    double gscale[64]; // accumulated feature gradient -> dF/d(feature) (SE: 1/(scale ell_b^2))
+    float sig2;        // sigma^2 * prod_b sigma_b^2 over SE blocks
+};
+
+// Arguments of the pair pass.
+struct PairPassArgs {
+    // query side (cluster view)
+    const float4 *qpts;
+    const float *qfeat;
+    const int2 *clus;     // (first sorted index, count)
+    const double4 *cgeo;  // (centre xyz in the query frame, radius)
+    const int *cpair;     // pair of each cluster
+    int nclus;
+    // reference side (grid view)
+    const float4 *rpts;
+    const float *rfeat;
+    const int *cell_start;
+    const GridDesc *grids;  // per pair
+    // per-pair pose applied to query points (query frame -> reference frame),
+    // and the pose in canonical orientation (Z frame -> X frame)
+    const PairState *state;
+    int pose_is_inverse;    // 0: query = Z (pose T); 1: query = X (pose T^-1)
+    float sig2;
+    double kappa;           // +inf: no cutoff
+    // outputs, indexed by the query's sorted position
+    double *oW;
+    double *oD;     // 3 per query
+    float *oS;      // 6 per query (forward mode)
+    int *oCnt;
+    double *oG;     // d4 per query (backward mode): feature gradients
+    double *oL;     // 1 per query (backward mode): sum w s'
+};
+
+}  // namespace cvo

@@ -1,0 +1,79 @@
+// cvo_launch.hpp -- host-side launchers of the device kernels (internal).
+#pragma once
+#include "cvo_internal.hpp"
+
+namespace cvo {
+
+struct CloudPtrs {
+    const float *xyz;
+    const float *feat;
+    long long n;
+};
+
+typedef GridDesc GridBuild;
+
+struct alignas(16) ClusterBuild {
+    double ox, oy, oz;  // Morton origin
+    double q;           // quantum (edge of a level-0 block)
+    long long pt_base;
+    long long n;
+};
+
+void launch_bbox(const CloudPtrs *clouds, int B, float *out, hipStream_t s);
+void launch_grid_keys(const CloudPtrs *clouds, const GridBuild *gb, int B, long long nmax,
+                      unsigned long long *keys, int *vals, int kbits, hipStream_t s);
+void launch_morton_keys(const CloudPtrs *clouds, const ClusterBuild *cb, int B, long long nmax,
+                        unsigned long long *keys, int *vals, int bits, hipStream_t s);
+void launch_exclusive_scan(const int *in, int *out, int *bsum, long long n, int *total, hipStream_t s);
+void launch_radix_sort(unsigned long long *keys, int *vals, unsigned long long *ktmp, int *vtmp, int *hist,
+                       int *bsum, long long n, int bits, hipStream_t s, bool *result_in_tmp);
+void launch_gather(const unsigned long long *keys, const int *vals, long long ntot, int cshift,
+                   const CloudPtrs *clouds, const long long *pt_base, const FeatLayout &lay, float4 *pts,
+                   float *feat, int *perm, hipStream_t s);
+void launch_cell_table(const unsigned long long *keys, long long ntot, const GridBuild *gb, int B,
+                       long long max_cells, int kbits, int *cell_start, hipStream_t s);
+void launch_cluster_heads(const unsigned long long *keys, long long ntot, const int *lcaps, int cshift, int tpw,
+                          int *head, int2 *span, hipStream_t s);
+void launch_cluster_emit(const int *head, const int *hidx, const int2 *span, const float4 *pts,
+                         const unsigned long long *keys, int cshift, long long ntot, int2 *clus, double4 *cgeo,
+                         int *cpair, hipStream_t s);
+
+// pair pass: mode 0 = forward moments, 1 = backward (feature gradients)
+// returns false when no kernel exists for the feature layout
+bool launch_pair_pass(const PairPassArgs &a, const FeatLayout &lay, int mode, hipStream_t s);
+
+struct ReduceArgs {
+    const float4 *qpts;
+    const ClusterDesc *cdesc;  // per pair: query points [pt_base, pt_base + n)
+    const double *W;
+    const double *D;
+    const float *S;
+    const int *cnt;
+    PairState *state;
+    const AlignConst *ac;
+    double *partials;          // B * nblk * kRedVals
+    unsigned int *counters;    // B, zero between launches
+    double *trace;             // B * trace_rows * kTraceLen, may be null
+    long long trace_rows;
+    int nblk;
+    int mode;                  // 0: evaluate only, 1: evaluate and take an ascent step
+};
+void launch_reduce(const ReduceArgs &a, int B, hipStream_t s);
+
+// backward post-processing
+struct BackwardArgs {
+    const int *qperm;         // sorted query index -> original index within its cloud
+    const double *D;          // 3 per sorted query (scaled units)
+    const double *G;          // d4 per sorted query
+    const PairState *state;
+    int pose_is_inverse;
+    FeatLayout lay;
+    double gF;
+    float *dxyz;              // original-order output, n x 3 (may be null)
+    float *dfeat;             // original-order output, n x src_dim (may be null)
+    long long n;
+};
+void launch_backward_finish(const BackwardArgs &a, hipStream_t s);
+void launch_sum_doubles(const double *in, long long n, double *out, hipStream_t s);
+
+}  // namespace cvo

@@ -1,0 +1,375 @@
+// cvo_pairs.hip -- the pair pass: the truncated double sum of eq. (7) and its
+// per-query moments, for one or many point-cloud pairs in one launch.
+//
+// Work decomposition (one 64-wide wavefront per query cluster):
+//   * The cluster's n <= 64 query points are transformed into the reference
+//     frame once (FP64), then re-expressed relative to the transformed
+//     cluster centre c' and scaled by sqrt(a), a = log2(e) / (2 ell^2), in
+//     FP32.  Relative coordinates are small, so FP32 keeps ~1e-7 of the
+//     cutoff radius even at 40 m from the origin.
+//   * Lanes are split into SUB = 64 / n' sub-streams (n' = n rounded up to a
+//     power of two); lane (q, t) pairs query t with every SUB-th candidate, so
+//     all 64 lanes stay busy for clusters of any size.
+//   * Candidates are the reference points in the grid cells overlapping the
+//     box around the ball of radius r_c + rho (rho: cluster radius).  The
+//     box's x-runs of cells are contiguous in the sorted reference array; up
+//     to 64 runs are measured at once (one per lane), prefix-summed, and
+//     their points loaded 64 at a time.  Points outside the ball are culled;
+//     survivors (coordinates and feature rows) are compacted with a ballot
+//     into a per-wave LDS queue.
+//   * When the queue holds >= 64 entries every lane walks its share: FP32
+//     squared distance, cutoff test, one exp2 for the geometric kernel and
+//     every SE feature block together, the LIN dot product, then FP64
+//     accumulation of W = sum w and D = sum w d, FP32 S = sum w d d^T.
+//   * Pairs whose FP32 squared distance lies within a proven error band of
+//     the cutoff are decided again with the FP64 expression that defines the
+//     pair set, so |P| is exact.
+//   * The sub-streams are combined with lane shuffles (fixed order, so the
+//     result is bitwise reproducible) and one lane per query writes its
+//     moments.
+#include "cvo_launch.hpp"
+
+namespace cvo {
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Membership of (x, z) in the pair set, decided exactly as the set is defined:
+// z'_r = ((R_r0 z0 + R_r1 z1) + R_r2 z2) + t_r, d = x - z',
+// s = (dx dx + dy dy) + dz dz, member iff s <= rc2; every operation is a
+// separately rounded IEEE double (contraction into FMA is switched off).
+__device__ __noinline__ bool canonical_member(const double *T, float x0, float x1, float x2, float z0,
+                                              float z1, float z2, double rc2)
+{
+#pragma clang fp contract(off)
+    const double a0 = (double)z0, a1 = (double)z1, a2 = (double)z2;
+    double zt[3];
+    for (int r = 0; r < 3; ++r) {
+        const double p = T[4 * r + 0] * a0;
+        const double q = T[4 * r + 1] * a1;
+        const double u = T[4 * r + 2] * a2;
+        zt[r] = ((p + q) + u) + T[4 * r + 3];
+    }
+    const double dx = (double)x0 - zt[0];
+    const double dy = (double)x1 - zt[1];
+    const double dz = (double)x2 - zt[2];
+    const double s = (dx * dx + dy * dy) + dz * dz;
+    return s <= rc2;
+}
+
+// Cells [i0, i1] along one axis covering [c - R, c + R]; false if none.
+__device__ __forceinline__ bool axis_range(double c, double R, double o, double h, int n, int &i0, int &i1)
+{
+    const double f0 = floor(((c - R) - o) / h);
+    const double f1 = floor(((c + R) - o) / h);
+    if (!(f1 >= 0.0) || !(f0 <= (double)(n - 1))) return false;
+    i0 = (int)fmax(f0, 0.0);
+    i1 = (int)fmin(f1, (double)(n - 1));
+    return true;
+}
+
+template <int SED, int LIND, int MODE>
+__global__ __launch_bounds__(kWave * kWavesPerBlock) void pair_pass_kernel(const PairPassArgs a)
+{
+    constexpr int D = SED + LIND;
+    constexpr int D4 = (D + 3) & ~3;
+    constexpr int F4 = D4 / 4;
+    constexpr int F4s = F4 > 0 ? F4 : 1;
+    constexpr int VF = D4 > 0 ? D4 : 1;
+    __shared__ float4 s_xyz[kWavesPerBlock][kQueueCap];
+    __shared__ float4 s_ft[kWavesPerBlock][kQueueCap * F4s];
+    __shared__ int s_src[kWavesPerBlock][kQueueCap];
+    __shared__ int s_rs[kWavesPerBlock][kWave];
+    __shared__ int s_rx[kWavesPerBlock][kWave];
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int c = wave_uniform(blockIdx.x * kWavesPerBlock + wv);
+    if (c >= a.nclus) return;
+    const int b = wave_uniform(a.cpair[c]);
+    const PairState *st = a.state + b;
+    if (st->done) return;
+
+    const double *P = a.pose_is_inverse ? st->Tinv : st->T;
+    double Pm[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) Pm[k] = P[k];
+    const double ell = st->ell;
+    const double ascale = 1.4426950408889634 / (2.0 * ell * ell);  // log2(e) / (2 ell^2)
+    const double sc = sqrt(ascale);
+    const bool cut = isfinite(a.kappa);
+    const double rc = a.kappa * ell;
+    const double rc2 = rc * rc;
+
+    const int2 cl = a.clus[c];
+    const double4 g = a.cgeo[c];
+    const double cx = Pm[0] * g.x + Pm[1] * g.y + Pm[2] * g.z + Pm[3];
+    const double cy = Pm[4] * g.x + Pm[5] * g.y + Pm[6] * g.z + Pm[7];
+    const double cz = Pm[8] * g.x + Pm[9] * g.y + Pm[10] * g.z + Pm[11];
+    const double rho = g.w;
+
+    // thresholds in scaled units: s' <= lo is certainly in P, s' > hi is
+    // certainly out; between them the FP64 definition decides.  The band is
+    // 8x the worst-case FP32 error 2^-24 (4 (1 + rho/rc) + 3) a rc^2 plus
+    // the rounding of the thresholds themselves.
+    float hi = INFINITY, lo = INFINITY, cull2 = INFINITY;
+    double Rm = INFINITY;
+    if (cut) {
+        const double u = 5.9604644775390625e-8;
+        const double G = u * (8.0 * (4.0 * (1.0 + rho / rc) + 3.0) + 4.0);
+        const double r2s = rc2 * ascale;
+        hi = (float)(r2s * (1.0 + G));
+        lo = (float)(r2s * (1.0 - G));
+        Rm = (rc + rho) * (1.0 + 1e-5);
+        cull2 = (float)(Rm * Rm * ascale);
+    }
+
+    // query point owned by this lane
+    const int n = cl.y;
+    const int np2 = (n <= 1) ? 1 : (1 << (32 - __clz(n - 1)));
+    const int lg = __ffs(np2) - 1;
+    const int t = lane & (np2 - 1);
+    const int qs = lane >> lg;
+    const int SUB = kWave >> lg;
+    const bool active = t < n;
+    const int pq = cl.x + (active ? t : 0);
+    const float4 zq = a.qpts[pq];
+    const double zpx = Pm[0] * zq.x + Pm[1] * zq.y + Pm[2] * zq.z + Pm[3];
+    const double zpy = Pm[4] * zq.x + Pm[5] * zq.y + Pm[6] * zq.z + Pm[7];
+    const double zpz = Pm[8] * zq.x + Pm[9] * zq.y + Pm[10] * zq.z + Pm[11];
+    const float zrx = (float)((zpx - cx) * sc);
+    const float zry = (float)((zpy - cy) * sc);
+    const float zrz = (float)((zpz - cz) * sc);
+    float vf[VF];
+#pragma unroll
+    for (int f = 0; f < F4; ++f) {
+        const float4 v4 = reinterpret_cast<const float4 *>(a.qfeat)[(long long)pq * F4 + f];
+        vf[4 * f + 0] = v4.x;
+        vf[4 * f + 1] = v4.y;
+        vf[4 * f + 2] = v4.z;
+        vf[4 * f + 3] = v4.w;
+    }
+
+    double W = 0.0, Dx = 0.0, Dy = 0.0, Dz = 0.0;
+    float S00 = 0.f, S01 = 0.f, S02 = 0.f, S11 = 0.f, S12 = 0.f, S22 = 0.f;
+    int cnt = 0;
+    double Gf[MODE == 1 ? VF : 1];
+    double Ls = 0.0;
+#pragma unroll
+    for (int k = 0; k < (MODE == 1 ? VF : 1); ++k) Gf[k] = 0.0;
+
+    const float sig2 = a.sig2;
+    const unsigned long long lt_mask = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
+
+    auto process = [&](int qn) {
+        for (int k = qs; k < qn; k += SUB) {
+            const float4 e = s_xyz[wv][k];
+            const float dx = e.x - zrx, dy = e.y - zry, dz = e.z - zrz;
+            const float s = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            if (active && s <= hi) {
+                bool pass = true;
+                if (s > lo) {
+                    const float4 rp = a.rpts[s_src[wv][k]];
+                    pass = a.pose_is_inverse
+                               ? canonical_member(st->T, zq.x, zq.y, zq.z, rp.x, rp.y, rp.z, rc2)
+                               : canonical_member(st->T, rp.x, rp.y, rp.z, zq.x, zq.y, zq.z, rc2);
+                }
+                if (pass) {
+                    float E = s;
+                    float lin = 0.0f;
+#pragma unroll
+                    for (int f = 0; f < F4; ++f) {
+                        const float4 u4 = s_ft[wv][k * F4 + f];
+                        const float uu[4] = {u4.x, u4.y, u4.z, u4.w};
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int d = 4 * f + q;
+                            if (d < SED) {
+                                const float df = uu[q] - vf[d];
+                                E = fmaf(df, df, E);
+                            } else if (d < D) {
+                                lin = fmaf(uu[q], vf[d], lin);
+                            }
+                        }
+                    }
+                    const float wnl = sig2 * __builtin_amdgcn_exp2f(-E);
+                    const float w = (LIND > 0) ? wnl * lin : wnl;
+                    W += (double)w;
+                    const float wx = w * dx, wy = w * dy, wz = w * dz;
+                    Dx += (double)wx;
+                    Dy += (double)wy;
+                    Dz += (double)wz;
+                    cnt += 1;
+                    if (MODE == 0) {
+                        S00 = fmaf(wx, dx, S00);
+                        S01 = fmaf(wx, dy, S01);
+                        S02 = fmaf(wx, dz, S02);
+                        S11 = fmaf(wy, dy, S11);
+                        S12 = fmaf(wy, dz, S12);
+                        S22 = fmaf(wz, dz, S22);
+                    } else {
+                        Ls += (double)(w * s);
+#pragma unroll
+                        for (int f = 0; f < F4; ++f) {
+                            const float4 u4 = s_ft[wv][k * F4 + f];
+                            const float uu[4] = {u4.x, u4.y, u4.z, u4.w};
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                const int d = 4 * f + q;
+                                if (MODE == 1 && d < SED) Gf[d] += (double)(w * (uu[q] - vf[d]));
+                                else if (MODE == 1 && d < D) Gf[d] += (double)(wnl * uu[q]);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    };
+
+    const GridDesc gd = a.grids[b];
+    int ix0 = 0, ix1 = gd.nx - 1, iy0 = 0, iy1 = gd.ny - 1, iz0 = 0, iz1 = gd.nz - 1;
+    bool any = gd.n > 0;
+    if (cut && any) {
+        any = axis_range(cx, Rm, gd.ox, gd.h, gd.nx, ix0, ix1) && axis_range(cy, Rm, gd.oy, gd.h, gd.ny, iy0, iy1) &&
+              axis_range(cz, Rm, gd.oz, gd.h, gd.nz, iz0, iz1);
+    }
+    int qn = 0;
+    if (any) {
+        const int nyr = iy1 - iy0 + 1;
+        const int nrows = nyr * (iz1 - iz0 + 1);
+        const int run = ix1 - ix0 + 1;
+        for (int rb = 0; rb < nrows; rb += kWave) {
+            const int r = rb + lane;
+            int rs = 0, len = 0;
+            if (r < nrows) {
+                const int iy = iy0 + r % nyr, iz = iz0 + r / nyr;
+                const long long k0 =
+                    (long long)gd.cell_base + ix0 + (long long)gd.nx * (iy + (long long)gd.ny * iz);
+                rs = a.cell_start[k0];
+                len = a.cell_start[k0 + run] - rs;
+            }
+            int incl = len;
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const int v = __shfl_up(incl, off);
+                if (lane >= off) incl += v;
+            }
+            const int total = __shfl(incl, kWave - 1);
+            s_rs[wv][lane] = rs;
+            s_rx[wv][lane] = incl - len;
+            wave_sync();
+            for (int m0 = 0; m0 < total; m0 += kWave) {
+                const int m = m0 + lane;
+                bool keep = false;
+                int src = 0;
+                float x0 = 0.f, x1 = 0.f, x2 = 0.f;
+                if (m < total) {
+                    int lo_ = 0, hi_ = kWave - 1;
+                    while (lo_ < hi_) {
+                        const int mid = (lo_ + hi_ + 1) >> 1;
+                        if (s_rx[wv][mid] <= m) lo_ = mid; else hi_ = mid - 1;
+                    }
+                    src = s_rs[wv][lo_] + (m - s_rx[wv][lo_]);
+                    const float4 xp = a.rpts[src];
+                    x0 = (float)(((double)xp.x - cx) * sc);
+                    x1 = (float)(((double)xp.y - cy) * sc);
+                    x2 = (float)(((double)xp.z - cz) * sc);
+                    keep = fmaf(x2, x2, fmaf(x1, x1, x0 * x0)) <= cull2;
+                }
+                const unsigned long long mask = __ballot(keep);
+                if (keep) {
+                    const int slot = qn + __popcll(mask & lt_mask);
+                    s_xyz[wv][slot] = make_float4(x0, x1, x2, 0.0f);
+                    s_src[wv][slot] = src;
+                    const float4 *fr = reinterpret_cast<const float4 *>(a.rfeat) + (long long)src * F4;
+#pragma unroll
+                    for (int f = 0; f < F4; ++f) s_ft[wv][slot * F4 + f] = fr[f];
+                }
+                qn += __popcll(mask);
+                wave_sync();
+                if (qn >= kQueueFlush) {
+                    process(qn);
+                    qn = 0;
+                    wave_sync();
+                }
+            }
+            wave_sync();
+        }
+    }
+    process(qn);
+
+    // combine the sub-streams of each query (fixed shuffle order)
+    for (int off = np2; off < kWave; off <<= 1) {
+        W += __shfl_xor(W, off);
+        Dx += __shfl_xor(Dx, off);
+        Dy += __shfl_xor(Dy, off);
+        Dz += __shfl_xor(Dz, off);
+        cnt += __shfl_xor(cnt, off);
+        if (MODE == 0) {
+            S00 += __shfl_xor(S00, off);
+            S01 += __shfl_xor(S01, off);
+            S02 += __shfl_xor(S02, off);
+            S11 += __shfl_xor(S11, off);
+            S12 += __shfl_xor(S12, off);
+            S22 += __shfl_xor(S22, off);
+        } else {
+            Ls += __shfl_xor(Ls, off);
+#pragma unroll
+            for (int k = 0; k < (MODE == 1 ? VF : 1); ++k) Gf[k] += __shfl_xor(Gf[k], off);
+        }
+    }
+    if (qs == 0 && active) {
+        a.oW[pq] = W;
+        a.oD[3 * (long long)pq + 0] = Dx;
+        a.oD[3 * (long long)pq + 1] = Dy;
+        a.oD[3 * (long long)pq + 2] = Dz;
+        a.oCnt[pq] = cnt;
+        if (MODE == 0) {
+            float *S = a.oS + 6 * (long long)pq;
+            S[0] = S00; S[1] = S01; S[2] = S02; S[3] = S11; S[4] = S12; S[5] = S22;
+        } else {
+            a.oL[pq] = Ls;
+#pragma unroll
+            for (int k = 0; k < (MODE == 1 ? D4 : 0); ++k) a.oG[(long long)pq * D4 + k] = Gf[k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- dispatch
+// Compiled feature layouts (SE columns, LIN columns); other layouts are
+// padded with zero columns up to the nearest compiled one.
+#define CVO_LAYOUTS(X)                                                                                     \
+    X(0, 0) X(0, 4) X(0, 19) X(0, 32) X(0, 64) X(5, 0) X(5, 4) X(5, 19) X(5, 32) X(8, 0) X(8, 4) X(8, 19)    \
+        X(8, 32) X(16, 0) X(16, 19) X(16, 32) X(32, 0) X(32, 19) X(32, 32)
+
+bool pair_layout_supported(int sed, int lind)
+{
+#define CVO_CHECK(S, L) if (sed == S && lind == L) return true;
+    CVO_LAYOUTS(CVO_CHECK)
+#undef CVO_CHECK
+    return false;
+}
+
+bool launch_pair_pass(const PairPassArgs &a, const FeatLayout &lay, int mode, hipStream_t s)
+{
+    if (a.nclus <= 0) return true;
+    const dim3 grid((a.nclus + kWavesPerBlock - 1) / kWavesPerBlock);
+    const dim3 block(kWave * kWavesPerBlock);
+#define CVO_LAUNCH(S, L)                                                                  \
+    if (lay.sed == S && lay.lind == L) {                                                  \
+        if (mode == 0) hipLaunchKernelGGL((pair_pass_kernel<S, L, 0>), grid, block, 0, s, a); \
+        else hipLaunchKernelGGL((pair_pass_kernel<S, L, 1>), grid, block, 0, s, a);           \
+        return true;                                                                      \
+    }
+    CVO_LAYOUTS(CVO_LAUNCH)
+#undef CVO_LAUNCH
+    return false;
+}
+
+}  // namespace cvo
