@@ -75,6 +75,13 @@ typedef enum {
 #define CVO_NO_OVERLAP 3 /* the pair set P became empty */
 #define CVO_STATIONARY 4 /* the gradient is exactly zero */
 
+/* metric on se(3) that turns the gradient into the ascent direction
+ * (cvo_align_params.metric); the paper names gradient ascent on the
+ * manifold (Sec. I) without fixing the metric */
+#define CVO_METRIC_KINETIC 0  /* G = mean_j J_j^T J_j: xi^T G xi is the mean squared velocity of the
+                                 moving cloud's points (rigid-body kinetic energy), direction G^-1 grad */
+#define CVO_METRIC_IDENTITY 1 /* plain coordinates: direction = grad */
+
 /* trace record per iteration (cvo_align trace buffer, doubles) */
 #define CVO_TRACE_LEN 8 /* it, ell, F, |grad|, step tau, i_theta, |P|, curvature */
 
@@ -112,7 +119,7 @@ typedef struct {
     double kappa;        /* cutoff in lengthscales */
     int64_t max_iter;    /* iteration cap, >= 1 */
     int32_t fixed_iters; /* nonzero: run exactly max_iter steps at ell_init, no annealing */
-    int32_t reserved;
+    int32_t metric;      /* CVO_METRIC_KINETIC (default) or CVO_METRIC_IDENTITY */
 } cvo_align_params;
 
 typedef struct {
@@ -143,7 +150,7 @@ typedef struct {
     double cluster_factor; /* cluster edge cap / cutoff radius, in [0.05, 2] */
     double rebuild_ratio;  /* rebuild grids when cutoff < rebuild_ratio * cutoff at build, in (0, 1] */
     int32_t unroll;        /* iterations enqueued per host check / per captured graph, 1..64 */
-    int32_t reserved;
+    int32_t piece_work;    /* query x candidate products per unit of pair-pass work, 256..2^24 */
 } cvo_tuning;
 
 /* Per-handle timing of the dominant kernel, measured with HIP events on the
@@ -194,10 +201,11 @@ cvo_status cvo_metric(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,
                       const double T[12], double *i_theta);
 
 /* Problem 1 (eq. (1)): gradient ascent on SE(3) from T_init with lengthscale
- * annealing (Sec. IV).  Per iteration: evaluate F, grad, curvature; step
- * tau = min(|g|^2 / -curv (if curv < 0, else +inf),
- *           step_lambda * ell / (|omega| r_max + |v|));
- * T <- Exp(tau grad) T; when the indicator has stabilised, ell <- max(ell_min,
+ * annealing (Sec. IV).  Per iteration: evaluate F and grad; direction
+ * d = G^-1 grad for the chosen metric G; curvature c of F(Exp(tau d) T);
+ * step tau = min(grad.d / -c (if c < 0, else +inf),
+ *                step_lambda * ell / (|d_omega| r_max + |d_v|));
+ * T <- Exp(tau d) T; when the indicator has stabilised, ell <- max(ell_min,
  * decay * ell).  T_out (host double[12]) and report (host) receive the
  * result; trace (host, may be NULL) receives max_iter x CVO_TRACE_LEN
  * doubles, of which report->iterations rows are written. */

@@ -23,6 +23,7 @@ _SRC = os.path.join(_HERE, "cvo_oracle.c")
 
 SE, LIN = 0, 1
 CONVERGED, MAX_ITER, NO_OVERLAP, STATIONARY = 1, 2, 3, 4
+METRIC_KINETIC, METRIC_IDENTITY = 0, 1
 EVAL_LEN, TRACE_LEN, REPORT_LEN = 18, 8, 6
 MAX_BLOCKS = 8
 
@@ -51,7 +52,7 @@ class _AlignParams(C.Structure):
     _fields_ = [("ell_init", C.c_double), ("ell_min", C.c_double), ("decay", C.c_double),
                 ("ind_rel_tol", C.c_double), ("eps_rot", C.c_double), ("eps_trans", C.c_double),
                 ("step_lambda", C.c_double), ("sigma", C.c_double), ("kappa", C.c_double),
-                ("max_iter", C.c_int64), ("fixed_iters", C.c_int32), ("pad_", C.c_int32)]
+                ("max_iter", C.c_int64), ("fixed_iters", C.c_int32), ("metric", C.c_int32)]
 
 
 _lib = None
@@ -69,6 +70,11 @@ def _load():
         lib.oracle_target_moments.argtypes = [P(_Cloud), P(_Cloud), P(_Spec), C.c_double, C.c_double,
                                               C.c_double, C.c_void_p, C.c_void_p, C.c_int64,
                                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        lib.oracle_evaluate_dir.argtypes = [P(_Cloud), P(_Cloud), P(_Spec), C.c_double, C.c_double,
+                                            C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, P(C.c_int64)]
+        lib.oracle_metric_tensor.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+        lib.oracle_metric_tensor.restype = None
+        lib.oracle_solve6.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         lib.oracle_exp_se3.argtypes = [C.c_void_p, C.c_void_p]
         lib.oracle_exp_se3.restype = None
         lib.oracle_transform.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
@@ -133,14 +139,19 @@ class _Pair:
         self.S = _spec(spec)
 
 
-def evaluate(x, u, z, v, spec, ell, T=None, sigma=1.0, kappa=3.0):
-    """F, gradient (omega, v), curvature along the gradient, dF/dell, |P| (eq. (7))."""
+def evaluate(x, u, z, v, spec, ell, T=None, sigma=1.0, kappa=3.0, direction=None):
+    """F, gradient (omega, v), curvature along the gradient (or along
+    `direction`), dF/dell, |P| (eq. (7))."""
     p = _Pair(x, u, z, v, spec)
     T = _pose(np.eye(4) if T is None else T)
     out = np.zeros(EVAL_LEN, np.float64)
     n = C.c_int64(0)
-    rc = _load().oracle_evaluate(C.byref(p.X), C.byref(p.Z), C.byref(p.S), ell, sigma, kappa,
-                                 T.ctypes.data, out.ctypes.data, C.byref(n))
+    dptr = None
+    if direction is not None:
+        dvec = np.ascontiguousarray(np.asarray(direction, np.float64).reshape(6))
+        dptr = dvec.ctypes.data
+    rc = _load().oracle_evaluate_dir(C.byref(p.X), C.byref(p.Z), C.byref(p.S), ell, sigma, kappa,
+                                     T.ctypes.data, dptr, out.ctypes.data, C.byref(n))
     if rc:
         raise ValueError(f"oracle_evaluate failed ({rc})")
     return {"F": out[0], "grad": out[1:7].copy(), "phi2": out[7], "dF_dell": out[8],
@@ -184,7 +195,25 @@ def transform(T, z):
 
 DEFAULT_ALIGN = dict(ell_init=0.1, ell_min=0.1, decay=0.98, ind_rel_tol=1e-3, eps_rot=1e-6,
                      eps_trans=1e-6, step_lambda=1.0, sigma=1.0, kappa=3.0, max_iter=4000,
-                     fixed_iters=False)
+                     fixed_iters=False, metric=METRIC_KINETIC)
+
+
+def metric_tensor(T, z):
+    """The kinetic-energy metric G of the moving cloud at pose T (6x6)."""
+    z = _f32(z, 3)
+    T = _pose(T)
+    G = np.zeros(36)
+    _load().oracle_metric_tensor(T.ctypes.data, z.ctypes.data, z.shape[0], G.ctypes.data)
+    return G.reshape(6, 6)
+
+
+def solve6(G, g):
+    G = np.ascontiguousarray(np.asarray(G, np.float64).reshape(36))
+    g = np.ascontiguousarray(np.asarray(g, np.float64).reshape(6))
+    d = np.zeros(6)
+    if _load().oracle_solve6(G.ctypes.data, g.ctypes.data, d.ctypes.data):
+        raise ValueError("singular metric")
+    return d
 
 
 def align(x, u, z, v, spec, params=None, T_init=None, trace=True):
@@ -194,7 +223,8 @@ def align(x, u, z, v, spec, params=None, T_init=None, trace=True):
     prm.update(params or {})
     ap = _AlignParams(prm["ell_init"], prm["ell_min"], prm["decay"], prm["ind_rel_tol"],
                       prm["eps_rot"], prm["eps_trans"], prm["step_lambda"], prm["sigma"],
-                      prm["kappa"], int(prm["max_iter"]), int(bool(prm["fixed_iters"])), 0)
+                      prm["kappa"], int(prm["max_iter"]), int(bool(prm["fixed_iters"])),
+                      int(prm["metric"]))
     T0 = _pose(np.eye(4) if T_init is None else T_init)
     Tout = np.zeros(12)
     rep = np.zeros(REPORT_LEN)

@@ -164,7 +164,7 @@ void oracle_transform(const double T[12], const float *z, int64_t M, double *zt)
 }
 
 /* ------------------------------------------------------------------ */
-/* F, gradient, curvature along the gradient, dF/dell (eq. (7)).
+/* F, gradient, curvature along a direction, dF/dell (eq. (7)).
  *
  * With z'_j = T z_j, d_ij = x_i - z'_j, s_ij = |d_ij|^2,
  *   w_ij   = c_ij * sigma^2 * exp(-s_ij / (2 ell^2))
@@ -174,33 +174,27 @@ void oracle_transform(const double T[12], const float *z, int64_t M, double *zt)
  *   dF/domega = ell^-2 sum w (z' x d) ,  dF/dv = ell^-2 sum w d
  *   d2F/deps2 = sum w [ (d.q)^2/ell^4 - |q|^2/ell^2 + d.(omega x q)/ell^2 ]
  *   dF/dell   = sum w s / ell^3     (cutoff radius held fixed)
- * Two passes: the curvature is taken along xi = gradient, known after pass 1. */
-int oracle_evaluate(const oracle_cloud *X, const oracle_cloud *Z, const oracle_spec *sp,
-                    double ell, double sigma, double kappa, const double T[12],
-                    double out[ORACLE_EVAL_LEN], int64_t *n_pairs)
+ * Pass 1 gives F and the gradient; pass 2 the curvature along a direction
+ * (the gradient unless one is given).                                     */
+typedef struct {
+    double acc[16];
+    int64_t np;
+    double rmax;
+} pass1_out;
+
+static int eval_pass1(const oracle_cloud *X, const oracle_cloud *Z, const oracle_spec *sp, double ell,
+                      double sigma, double kappa, const double *zt, pass1_out *res)
 {
-    if (!(ell > 0.0) || !(sigma > 0.0) || !(kappa > 0.0)) return -1;
+    enum { NACC = 16 };
     const int D = spec_dim(sp);
     const int64_t N = X->n, M = Z->n;
     const double rc2 = cutoff_sq(ell, kappa);
     const double il2 = 1.0 / (ell * ell);
     const double s2 = sigma * sigma;
-    double *zt = (double *)malloc(sizeof(double) * 3 * (M > 0 ? M : 1));
-    if (!zt) return -2;
-    oracle_transform(T, Z->xyz, M, zt);
-
-    double rmax = 0.0;
-    for (int64_t j = 0; j < M; ++j) {
-        double r = sqrt(dot3(zt + 3 * j, zt + 3 * j));
-        if (r > rmax) rmax = r;
-    }
-
-    enum { NACC = 16 };
     const int nt = nthreads();
     double *part = (double *)calloc((size_t)nt * NACC, sizeof(double));
     int64_t *pcount = (int64_t *)calloc((size_t)nt, sizeof(int64_t));
-
-    /* pass 1: F, gradient, abs-sums, dF/dell, pair count */
+    if (!part || !pcount) { free(part); free(pcount); return -2; }
 #pragma omp parallel
     {
         double *a = part + (size_t)thread_id() * NACC;
@@ -230,28 +224,42 @@ int oracle_evaluate(const oracle_cloud *X, const oracle_cloud *Z, const oracle_s
         }
         pcount[thread_id()] = cnt;
     }
-    double acc[NACC];
-    memset(acc, 0, sizeof(acc));
-    int64_t total = 0;
+    memset(res, 0, sizeof(*res));
     for (int t = 0; t < nt; ++t) {
-        for (int k = 0; k < NACC; ++k) acc[k] += part[(size_t)t * NACC + k];
-        total += pcount[t];
+        for (int k = 0; k < NACC; ++k) res->acc[k] += part[(size_t)t * NACC + k];
+        res->np += pcount[t];
     }
+    for (int64_t j = 0; j < M; ++j) {
+        double r = sqrt(dot3(zt + 3 * j, zt + 3 * j));
+        if (r > res->rmax) res->rmax = r;
+    }
+    free(part);
+    free(pcount);
+    return 0;
+}
 
-    /* pass 2: curvature along xi = (omega, v) = gradient */
-    const double om[3] = {acc[1], acc[2], acc[3]};
-    const double vv[3] = {acc[4], acc[5], acc[6]};
+static double eval_curvature(const oracle_cloud *X, const oracle_cloud *Z, const oracle_spec *sp, double ell,
+                             double sigma, double kappa, const double *zt, const double xi[6])
+{
+    const int D = spec_dim(sp);
+    const int64_t N = X->n, M = Z->n;
+    const double rc2 = cutoff_sq(ell, kappa);
+    const double il2 = 1.0 / (ell * ell);
+    const double s2 = sigma * sigma;
+    const double om[3] = {xi[0], xi[1], xi[2]};
+    const double vv[3] = {xi[3], xi[4], xi[5]};
+    const int nt = nthreads();
     double *cpart = (double *)calloc((size_t)nt, sizeof(double));
 #pragma omp parallel
     {
         double a = 0.0;
 #pragma omp for schedule(static)
         for (int64_t i = 0; i < N; ++i) {
-            const float *xi = X->xyz + 3 * i;
+            const float *xi_ = X->xyz + 3 * i;
             const float *ui = D ? X->feat + (size_t)D * i : NULL;
             for (int64_t j = 0; j < M; ++j) {
                 double d[3];
-                double s = canonical_distance(xi, zt + 3 * j, d);
+                double s = canonical_distance(xi_, zt + 3 * j, d);
                 if (!(s <= rc2)) continue;
                 const float *vj = D ? Z->feat + (size_t)D * j : NULL;
                 double c = feature_kernel(sp, ui, vj, NULL);
@@ -268,20 +276,44 @@ int oracle_evaluate(const oracle_cloud *X, const oracle_cloud *Z, const oracle_s
     }
     double phi2 = 0.0;
     for (int t = 0; t < nt; ++t) phi2 += cpart[t];
-
-    out[ORACLE_F] = acc[0];
-    for (int k = 0; k < 6; ++k) out[ORACLE_G + k] = acc[1 + k];
-    out[ORACLE_PHI2] = phi2;
-    out[ORACLE_DELL] = acc[7];
-    out[ORACLE_ABSF] = acc[8];
-    for (int k = 0; k < 6; ++k) out[ORACLE_ABSG + k] = acc[9 + k];
-    out[ORACLE_RMAX] = rmax;
-    out[ORACLE_ITHETA] = (N > 0 && M > 0) ? acc[0] / sqrt((double)N * (double)M) : 0.0;
-    *n_pairs = total;
-
     free(cpart);
-    free(part);
-    free(pcount);
+    return phi2;
+}
+
+int oracle_evaluate(const oracle_cloud *X, const oracle_cloud *Z, const oracle_spec *sp,
+                    double ell, double sigma, double kappa, const double T[12],
+                    double out[ORACLE_EVAL_LEN], int64_t *n_pairs)
+{
+    return oracle_evaluate_dir(X, Z, sp, ell, sigma, kappa, T, NULL, out, n_pairs);
+}
+
+/* As oracle_evaluate, with the curvature taken along `dir` (6 doubles,
+ * omega then v) instead of along the gradient when dir is not NULL. */
+int oracle_evaluate_dir(const oracle_cloud *X, const oracle_cloud *Z, const oracle_spec *sp,
+                        double ell, double sigma, double kappa, const double T[12],
+                        const double *dir, double out[ORACLE_EVAL_LEN], int64_t *n_pairs)
+{
+    if (!(ell > 0.0) || !(sigma > 0.0) || !(kappa > 0.0)) return -1;
+    const int64_t N = X->n, M = Z->n;
+    double *zt = (double *)malloc(sizeof(double) * 3 * (M > 0 ? M : 1));
+    if (!zt) return -2;
+    oracle_transform(T, Z->xyz, M, zt);
+    pass1_out p;
+    int rc = eval_pass1(X, Z, sp, ell, sigma, kappa, zt, &p);
+    if (rc) { free(zt); return rc; }
+    double xi[6];
+    for (int k = 0; k < 6; ++k) xi[k] = dir ? dir[k] : p.acc[1 + k];
+    const double phi2 = eval_curvature(X, Z, sp, ell, sigma, kappa, zt, xi);
+
+    out[ORACLE_F] = p.acc[0];
+    for (int k = 0; k < 6; ++k) out[ORACLE_G + k] = p.acc[1 + k];
+    out[ORACLE_PHI2] = phi2;
+    out[ORACLE_DELL] = p.acc[7];
+    out[ORACLE_ABSF] = p.acc[8];
+    for (int k = 0; k < 6; ++k) out[ORACLE_ABSG + k] = p.acc[9 + k];
+    out[ORACLE_RMAX] = p.rmax;
+    out[ORACLE_ITHETA] = (N > 0 && M > 0) ? p.acc[0] / sqrt((double)N * (double)M) : 0.0;
+    *n_pairs = p.np;
     free(zt);
     return 0;
 }
@@ -327,6 +359,68 @@ int oracle_target_moments(const oracle_cloud *X, const oracle_cloud *Z, const or
         for (int k = 0; k < 3; ++k) Dm[3 * q + k] = d_[k];
         for (int k = 0; k < 6; ++k) S[6 * q + k] = s_[k];
         cnt[q] = c_;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Metric on se(3) used for the ascent direction: the kinetic energy of the
+ * moving cloud as a rigid body with unit masses,
+ *   xi^T G xi = (1/M) sum_j |omega x z'_j + v|^2,  G = (1/M) sum_j J_j^T J_j,
+ *   J_j = [ -[z'_j]_x  I ],
+ * plus mu = 1e-6 (mean |z'|^2 + 1e-12) on the rotation block, which keeps G
+ * positive definite for collinear or single-point clouds.  The Riemannian
+ * gradient is G^-1 grad.                                                  */
+void oracle_metric_tensor(const double T[12], const float *z, int64_t M, double G[36])
+{
+    for (int k = 0; k < 36; ++k) G[k] = 0.0;
+    double r2 = 0.0;
+    for (int64_t j = 0; j < M; ++j) {
+        double zt[3];
+        canonical_transform(T, z + 3 * j, zt);
+        double J[3][6];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 6; ++c) J[r][c] = 0.0;
+        /* -[z]_x */
+        J[0][1] = zt[2];  J[0][2] = -zt[1];
+        J[1][0] = -zt[2]; J[1][2] = zt[0];
+        J[2][0] = zt[1];  J[2][1] = -zt[0];
+        J[0][3] = 1.0; J[1][4] = 1.0; J[2][5] = 1.0;
+        for (int a = 0; a < 6; ++a)
+            for (int b = 0; b < 6; ++b) G[6 * a + b] += J[0][a] * J[0][b] + J[1][a] * J[1][b] + J[2][a] * J[2][b];
+        r2 += dot3(zt, zt);
+    }
+    const double inv = M > 0 ? 1.0 / (double)M : 0.0;
+    for (int k = 0; k < 36; ++k) G[k] *= inv;
+    const double mu = 1e-6 * (r2 * inv + 1e-12);
+    for (int a = 0; a < 3; ++a) G[7 * a] += mu;
+}
+
+/* Solve G d = g for a symmetric positive definite 6x6 G (Gaussian
+ * elimination with partial pivoting).  Returns nonzero if G is singular. */
+int oracle_solve6(const double G[36], const double g[6], double d[6])
+{
+    double A[6][7];
+    for (int r = 0; r < 6; ++r) {
+        for (int c = 0; c < 6; ++c) A[r][c] = G[6 * r + c];
+        A[r][6] = g[r];
+    }
+    for (int c = 0; c < 6; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 6; ++r)
+            if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+        if (A[piv][c] == 0.0) return -1;
+        if (piv != c)
+            for (int k = 0; k < 7; ++k) { double t = A[c][k]; A[c][k] = A[piv][k]; A[piv][k] = t; }
+        for (int r = c + 1; r < 6; ++r) {
+            double f = A[r][c] / A[c][c];
+            for (int k = c; k < 7; ++k) A[r][k] -= f * A[c][k];
+        }
+    }
+    for (int r = 5; r >= 0; --r) {
+        double s = A[r][6];
+        for (int k = r + 1; k < 6; ++k) s -= A[r][k] * d[k];
+        d[r] = s / A[r][r];
     }
     return 0;
 }
@@ -389,13 +483,16 @@ static void compose_left(const double B[12], double A[12])
 /* ------------------------------------------------------------------ */
 /* Problem 1 by gradient ascent on SE(3) with lengthscale annealing.
  * Per iteration, at the current (T, ell):
- *   a. evaluate F, g = (omega, v), curvature phi'' along g, |P|.
- *      |P| = 0 -> NO_OVERLAP; |g| = 0 -> STATIONARY (no step).
+ *   a. evaluate F, the gradient g = (omega, v) and |P|.
+ *      |P| = 0 -> NO_OVERLAP; g = 0 -> STATIONARY (no step).
  *   b. indicator i = F / sqrt(|X||Z|)                         (eq. (10))
- *   c. tau_N = |g|^2 / (-phi'') if phi'' < 0, else +inf;
- *      tau_C = lambda * ell / (|omega| * r_max + |v|), r_max = max_j |z'_j|;
+ *   c. ascent direction d = G^-1 g, the Riemannian gradient for the metric G
+ *      (kinetic-energy metric of the moving cloud, or the identity), and the
+ *      curvature phi'' of F(Exp(tau d) T) at tau = 0;
+ *      tau_N = (g.d) / (-phi'') if phi'' < 0, else +inf;
+ *      tau_C = lambda * ell / (|d_omega| * r_max + |d_v|), r_max = max_j |z'_j|;
  *      tau = min(tau_N, tau_C)
- *   d. T <- Exp(tau g) T
+ *   d. T <- Exp(tau d) T
  *   e. annealing (Sec. IV): when the indicator has stabilised at the current
  *      lengthscale, ell <- max(ell_min, decay * ell) and the reference
  *      indicator is cleared; otherwise it becomes the reference.
@@ -414,10 +511,10 @@ int oracle_align(const oracle_cloud *X, const oracle_cloud *Z, const oracle_spec
     double i_prev = NAN;
     int64_t it = 0;
     int status = ORACLE_MAX_ITER;
-    double out[ORACLE_EVAL_LEN];
     int64_t np = 0;
     double last_F = 0.0, last_i = 0.0;
-    if (X->n == 0 || Z->n == 0) {
+    const int64_t M = Z->n;
+    if (X->n == 0 || M == 0) {
         memcpy(T_out, T_init, sizeof(double) * 12);
         report[0] = 0;
         report[1] = ell;
@@ -427,30 +524,44 @@ int oracle_align(const oracle_cloud *X, const oracle_cloud *Z, const oracle_spec
         report[5] = ORACLE_NO_OVERLAP;
         return 0;
     }
+    double *zt = (double *)malloc(sizeof(double) * 3 * M);
+    if (!zt) return -2;
     while (it < ap->max_iter) {
-        int rc = oracle_evaluate(X, Z, sp, ell, ap->sigma, ap->kappa, T, out, &np);
-        if (rc) return rc;
-        last_F = out[ORACLE_F];
-        last_i = out[ORACLE_ITHETA];
+        oracle_transform(T, Z->xyz, M, zt);
+        pass1_out p;
+        int rc = eval_pass1(X, Z, sp, ell, ap->sigma, ap->kappa, zt, &p);
+        if (rc) { free(zt); return rc; }
+        np = p.np;
+        last_F = p.acc[0];
+        last_i = p.acc[0] / sqrt((double)X->n * (double)M);
         if (np == 0) { status = ORACLE_NO_OVERLAP; break; }
-        const double *g = out + ORACLE_G;
+        const double *g = p.acc + 1;
         const double gn2 = dot3(g, g) + dot3(g + 3, g + 3);
         if (gn2 == 0.0) { status = ORACLE_STATIONARY; break; }
-        const double ind = out[ORACLE_ITHETA];
-        const double phi2 = out[ORACLE_PHI2];
-        const double tauN = (phi2 < 0.0) ? gn2 / (-phi2) : INFINITY;
-        const double nw = sqrt(dot3(g, g)), nv = sqrt(dot3(g + 3, g + 3));
-        const double tauC = ap->step_lambda * ell / (nw * out[ORACLE_RMAX] + nv);
+        const double ind = last_i;
+        double d[6];
+        if (ap->metric == ORACLE_METRIC_KINETIC) {
+            double G[36];
+            oracle_metric_tensor(T, Z->xyz, M, G);
+            if (oracle_solve6(G, g, d)) { free(zt); return -3; }
+        } else {
+            for (int k = 0; k < 6; ++k) d[k] = g[k];
+        }
+        const double slope = dot3(g, d) + dot3(g + 3, d + 3);
+        const double phi2 = eval_curvature(X, Z, sp, ell, ap->sigma, ap->kappa, zt, d);
+        const double tauN = (phi2 < 0.0) ? slope / (-phi2) : INFINITY;
+        const double nw = sqrt(dot3(d, d)), nv = sqrt(dot3(d + 3, d + 3));
+        const double tauC = ap->step_lambda * ell / (nw * p.rmax + nv);
         const double tau = tauN < tauC ? tauN : tauC;
         double xi[6], E[12];
-        for (int k = 0; k < 6; ++k) xi[k] = tau * g[k];
+        for (int k = 0; k < 6; ++k) xi[k] = tau * d[k];
         oracle_exp_se3(xi, E);
         compose_left(E, T);
         if (trace) {
             double *tr = trace + (size_t)it * ORACLE_TRACE_LEN;
             tr[0] = (double)it;
             tr[1] = ell;
-            tr[2] = out[ORACLE_F];
+            tr[2] = p.acc[0];
             tr[3] = sqrt(gn2);
             tr[4] = tau;
             tr[5] = ind;
@@ -473,6 +584,7 @@ int oracle_align(const oracle_cloud *X, const oracle_cloud *Z, const oracle_spec
             }
         }
     }
+    free(zt);
     memcpy(T_out, T, sizeof(T));
     report[0] = (double)it;
     report[1] = ell;

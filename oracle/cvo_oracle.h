@@ -16,6 +16,10 @@
 #define ORACLE_NO_OVERLAP 3
 #define ORACLE_STATIONARY 4
 
+/* metric on se(3) for the ascent direction */
+#define ORACLE_METRIC_KINETIC 0  /* mean squared point velocity of the moving cloud */
+#define ORACLE_METRIC_IDENTITY 1 /* plain coordinates (omega, v) */
+
 /* layout of oracle_evaluate's output vector */
 #define ORACLE_F 0
 #define ORACLE_G 1      /* 6: omega xyz, v xyz */
@@ -50,7 +54,7 @@ typedef struct {
     double sigma, kappa;
     int64_t max_iter;
     int32_t fixed_iters;
-    int32_t pad_;
+    int32_t metric;
 } oracle_align_params;
 
 int oracle_num_threads(void);
@@ -58,6 +62,11 @@ void oracle_transform(const double T[12], const float *z, int64_t M, double *zt)
 int oracle_evaluate(const oracle_cloud *X, const oracle_cloud *Z, const oracle_spec *sp,
                     double ell, double sigma, double kappa, const double T[12],
                     double out[ORACLE_EVAL_LEN], int64_t *n_pairs);
+int oracle_evaluate_dir(const oracle_cloud *X, const oracle_cloud *Z, const oracle_spec *sp,
+                        double ell, double sigma, double kappa, const double T[12],
+                        const double *dir, double out[ORACLE_EVAL_LEN], int64_t *n_pairs);
+void oracle_metric_tensor(const double T[12], const float *z, int64_t M, double G[36]);
+int oracle_solve6(const double G[36], const double g[6], double d[6]);
 int oracle_target_moments(const oracle_cloud *X, const oracle_cloud *Z, const oracle_spec *sp,
                           double ell, double sigma, double kappa, const double T[12],
                           const int64_t *idx, int64_t nidx, double *W, double *D, double *S,

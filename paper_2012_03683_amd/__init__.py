@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libcvo_hip.so")
 CVO_OK, CVO_ERR_INVALID_ARGUMENT, CVO_ERR_OUT_OF_MEMORY, CVO_ERR_DEVICE, CVO_ERR_UNSUPPORTED = range(5)
 CVO_SE, CVO_LIN = 0, 1
 CVO_CONVERGED, CVO_MAX_ITER, CVO_NO_OVERLAP, CVO_STATIONARY = 1, 2, 3, 4
+CVO_METRIC_KINETIC, CVO_METRIC_IDENTITY = 0, 1
 CVO_TRACE_LEN = 8
 MAX_BLOCKS = 8
 
@@ -58,7 +59,7 @@ class cvo_align_params(C.Structure):
     _fields_ = [("ell_init", C.c_double), ("ell_min", C.c_double), ("decay", C.c_double),
                 ("ind_rel_tol", C.c_double), ("eps_rot", C.c_double), ("eps_trans", C.c_double),
                 ("step_lambda", C.c_double), ("sigma", C.c_double), ("kappa", C.c_double),
-                ("max_iter", C.c_int64), ("fixed_iters", C.c_int32), ("reserved", C.c_int32)]
+                ("max_iter", C.c_int64), ("fixed_iters", C.c_int32), ("metric", C.c_int32)]
 
 
 class cvo_align_report(C.Structure):
@@ -74,7 +75,7 @@ class cvo_eval(C.Structure):
 
 class cvo_tuning(C.Structure):
     _fields_ = [("cluster_max", C.c_int32), ("cell_factor", C.c_double), ("cluster_factor", C.c_double),
-                ("rebuild_ratio", C.c_double), ("unroll", C.c_int32), ("reserved", C.c_int32)]
+                ("rebuild_ratio", C.c_double), ("unroll", C.c_int32), ("piece_work", C.c_int32)]
 
 
 class cvo_timing(C.Structure):
@@ -279,7 +280,8 @@ def cvo_metric(X, Z, T, ell, U=None, V=None, spec=None, sigma=1.0, kappa=3.0):
 
 
 DEFAULT_ALIGN = dict(ell_init=0.1, ell_min=0.1, decay=0.98, ind_rel_tol=1e-3, eps_rot=1e-6, eps_trans=1e-6,
-                     step_lambda=1.0, sigma=1.0, kappa=3.0, max_iter=4000, fixed_iters=False)
+                     step_lambda=1.0, sigma=1.0, kappa=3.0, max_iter=4000, fixed_iters=False,
+                     metric=CVO_METRIC_KINETIC)
 
 
 def _align_params(params):
@@ -287,7 +289,7 @@ def _align_params(params):
     p.update(params or {})
     return cvo_align_params(p["ell_init"], p["ell_min"], p["decay"], p["ind_rel_tol"], p["eps_rot"],
                             p["eps_trans"], p["step_lambda"], p["sigma"], p["kappa"], int(p["max_iter"]),
-                            int(bool(p["fixed_iters"])), 0), p
+                            int(bool(p["fixed_iters"])), int(p["metric"])), p
 
 
 def _report(r):

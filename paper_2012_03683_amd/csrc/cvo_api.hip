@@ -61,15 +61,17 @@ struct cvo_context {
     unsigned long long generation = 0;  // bumps whenever a buffer moves
     void *pinned = nullptr;
     size_t pinned_cap = 0;
-    cvo_tuning tuning{16, 1.0, 0.5, 0.5, 8, 0};
+    cvo_tuning tuning{16, 1.0, 0.5, 0.5, 8, 16384};
     bool profiling = false;
     cvo_timing timing{0, 0.0, 0, 0};
     std::vector<hipEvent_t> ev_free;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
     std::map<std::string, cvo_tuning> tune_cache;
-    // captured batched graph
+    // captured batched graph, and the library-owned stream it is captured on
+    // (the legacy default stream cannot be captured)
     hipGraphExec_t graph = nullptr;
     std::string graph_key;
+    hipStream_t own_stream = nullptr;
 
     void *get(const std::string &name, size_t bytes)
     {
@@ -152,10 +154,17 @@ struct cvo_context {
         }
         ev_pending.clear();
     }
+    hipStream_t capture_stream()
+    {
+        if (!own_stream) HIP_OK(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
+        return own_stream;
+    }
     void release()
     {
         if (graph) hipGraphExecDestroy(graph);
         graph = nullptr;
+        if (own_stream) hipStreamDestroy(own_stream);
+        own_stream = nullptr;
         for (auto &kv : bufs)
             if (kv.second.p) hipFree(kv.second.p);
         bufs.clear();
@@ -309,6 +318,7 @@ struct ClusterView {
     int2 *clus = nullptr;
     double4 *cgeo = nullptr;
     int *cpair = nullptr;
+    int *tclus = nullptr;  // cluster of every sorted point
     int nclus = 0;
     long long ntot = 0;
     std::vector<double> rc;
@@ -504,6 +514,7 @@ ClusterView build_clusters(cvo_context *ctx, const std::string &pre, const std::
     v.clus = ctx->get_t<int2>(pre + ".clus", ntot);
     v.cgeo = ctx->get_t<double4>(pre + ".cgeo", ntot);
     v.cpair = ctx->get_t<int>(pre + ".cpair", ntot);
+    v.tclus = ctx->get_t<int>(pre + ".tclus", ntot);
     int *head = ctx->get_t<int>(pre + ".head", ntot);
     int *hidx = ctx->get_t<int>(pre + ".hidx", ntot);
     int2 *span = ctx->get_t<int2>(pre + ".span", ntot);
@@ -517,7 +528,8 @@ ClusterView build_clusters(cvo_context *ctx, const std::string &pre, const std::
         launch_gather(keys, vals, v.ntot, 3 * bits, dc, d_base, lay, v.pts, v.feat, v.perm, ctx->stream);
         launch_cluster_heads(keys, v.ntot, d_lcap, 3 * bits, tpw, head, span, ctx->stream);
         launch_exclusive_scan(head, hidx, bsum, v.ntot, d_total, ctx->stream);
-        launch_cluster_emit(head, hidx, span, v.pts, keys, 3 * bits, v.ntot, v.clus, v.cgeo, v.cpair, ctx->stream);
+        launch_cluster_emit(head, hidx, span, v.pts, keys, 3 * bits, v.ntot, v.clus, v.cgeo, v.cpair, v.tclus,
+                            ctx->stream);
         ctx->check_launch("cluster build");
         int total = 0;
         ctx->download(&total, d_total, sizeof(int));
@@ -525,6 +537,74 @@ ClusterView build_clusters(cvo_context *ctx, const std::string &pre, const std::
     }
     ctx->upload(v.d_desc, v.desc.data(), sizeof(ClusterDesc) * B);
     return v;
+}
+
+// ------------------------------------------------------------------ work plan
+// Pieces: every cluster's candidate list is cut into ranges of about
+// `piece_work` query x candidate products (planned at the pose in the device
+// state), and the pieces are processed heaviest first.
+struct Plan {
+    int4 *pieces = nullptr;
+    int *porder = nullptr;
+    int2 *cpieces = nullptr;
+    int npieces = 0;
+    long long nslots = 0;
+    unsigned int *ticket = nullptr;
+};
+
+Plan make_plan(cvo_context *ctx, const std::string &pre, const ClusterView &q, const GridView &r,
+               const PairState *d_state, int inverse, double kappa)
+{
+    Plan pl;
+    pl.ticket = ctx->get_t<unsigned int>(pre + ".ticket", 1);
+    if (q.nclus == 0) return pl;
+    PairPassArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.clus = q.clus;
+    a.cgeo = q.cgeo;
+    a.cpair = q.cpair;
+    a.nclus = q.nclus;
+    a.cell_start = r.cell_start;
+    a.grids = r.d_desc;
+    a.state = d_state;
+    a.pose_is_inverse = inverse;
+    a.kappa = kappa;
+    const int nc = q.nclus;
+    int *npc = ctx->get_t<int>(pre + ".npc", nc);
+    int *cmax = ctx->get_t<int>(pre + ".cmax", nc);
+    long long *ccount = ctx->get_t<long long>(pre + ".ccount", nc);
+    int *pbase = ctx->get_t<int>(pre + ".pbase", nc);
+    int *bsum = ctx->get_t<int>(pre + ".pbsum", (nc + 2047) / 2048 + 1);
+    int *d_total = ctx->get_t<int>(pre + ".ptotal", 2);
+    launch_plan_count(a, ctx->tuning.piece_work, npc, cmax, ccount, ctx->stream);
+    launch_exclusive_scan(npc, pbase, bsum, nc, d_total, ctx->stream);
+    ctx->check_launch("plan count");
+    int P = 0;
+    ctx->download(&P, d_total, sizeof(int));
+    pl.npieces = P;
+    pl.pieces = ctx->get_t<int4>(pre + ".pieces", P);
+    int *pn = ctx->get_t<int>(pre + ".pn", P);
+    int *tbase = ctx->get_t<int>(pre + ".tbase", P);
+    unsigned long long *key = ctx->get_t<unsigned long long>(pre + ".pkey", P);
+    unsigned long long *ktmp = ctx->get_t<unsigned long long>(pre + ".pktmp", P);
+    int *val = ctx->get_t<int>(pre + ".pval", P);
+    int *vtmp = ctx->get_t<int>(pre + ".pvtmp", P);
+    const long long ntiles = (P + 4095) / 4096;
+    int *hist = ctx->get_t<int>(pre + ".phist", ntiles * 256);
+    int *bsum2 = ctx->get_t<int>(pre + ".pbsum2", (std::max<long long>(ntiles * 256, P) + 2047) / 2048 + 1);
+    pl.cpieces = ctx->get_t<int2>(pre + ".cpieces", nc);
+    launch_plan_emit(a, npc, pbase, cmax, ccount, pl.pieces, pn, key, val, pl.cpieces, ctx->stream);
+    launch_exclusive_scan(pn, tbase, bsum2, P, d_total + 1, ctx->stream);
+    launch_plan_slots(pl.pieces, tbase, P, ctx->stream);
+    bool in_tmp = false;
+    launch_radix_sort(key, val, ktmp, vtmp, hist, bsum2, P, 32, ctx->stream, &in_tmp);
+    pl.porder = in_tmp ? vtmp : val;
+    ctx->check_launch("plan emit");
+    int S = 0;
+    ctx->download(&S, d_total + 1, sizeof(int));
+    pl.nslots = S;
+    HIP_OK(hipMemsetAsync(pl.ticket, 0, sizeof(unsigned int), ctx->stream));
+    return pl;
 }
 
 // ------------------------------------------------------------------ pair pass + reduce
@@ -553,7 +633,7 @@ Moments moments(cvo_context *ctx, const std::string &pre, long long n, int d4, b
 }
 
 PairPassArgs pass_args(const ClusterView &q, const GridView &r, const PairState *st, int inverse, float sig2,
-                       double kappa, const Moments &m)
+                       double kappa, const Moments &m, const Plan &pl)
 {
     PairPassArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -577,7 +657,21 @@ PairPassArgs pass_args(const ClusterView &q, const GridView &r, const PairState 
     a.oCnt = m.cnt;
     a.oG = m.G;
     a.oL = m.L;
+    a.pieces = pl.pieces;
+    a.porder = pl.porder;
+    a.npieces = pl.npieces;
+    a.ticket = pl.ticket;
     return a;
+}
+
+SlotMap slot_map(const ClusterView &q, const Plan &pl)
+{
+    SlotMap m;
+    m.tclus = q.tclus;
+    m.clus = q.clus;
+    m.cpieces = pl.cpieces;
+    m.pieces = pl.pieces;
+    return m;
 }
 
 void run_pair_pass(cvo_context *ctx, const PairPassArgs &a, const FeatLayout &lay, int mode)
@@ -627,6 +721,7 @@ struct Problem {
     FeatLayout lay;
     GridView grid;       // X clouds, reference role
     ClusterView clus;    // Z clouds, query role
+    Plan plan;
     Moments mom;
     PairState *d_state = nullptr;
     AlignConst *d_ac = nullptr;
@@ -637,6 +732,8 @@ struct Problem {
     float sig2 = 1.f;
 };
 
+// Grid of X, clusters of Z, and the work plan at the pose held in the device
+// state (which must be current).
 void build_views(cvo_context *ctx, Problem &p, const std::vector<CloudPtrs> &X, const std::vector<CloudPtrs> &Z,
                  const std::vector<double> &ell)
 {
@@ -644,7 +741,8 @@ void build_views(cvo_context *ctx, Problem &p, const std::vector<CloudPtrs> &X, 
     for (size_t k = 0; k < ell.size(); ++k) rc[k] = p.kappa * ell[k];
     p.grid = build_grid(ctx, "fx", X, rc, p.lay);
     p.clus = build_clusters(ctx, "fz", Z, rc, p.lay);
-    p.mom = moments(ctx, "fm", p.clus.ntot, p.lay.d4, false);
+    p.plan = make_plan(ctx, "fp", p.clus, p.grid, p.d_state, 0, p.kappa);
+    p.mom = moments(ctx, "fm", p.plan.nslots, p.lay.d4, false);
 }
 
 void setup_problem(cvo_context *ctx, Problem &p, const std::vector<CloudPtrs> &X, const std::vector<CloudPtrs> &Z,
@@ -653,9 +751,9 @@ void setup_problem(cvo_context *ctx, Problem &p, const std::vector<CloudPtrs> &X
     const int B = (int)X.size();
     std::vector<double> ell(B);
     for (int b = 0; b < B; ++b) ell[b] = st[b].ell;
-    build_views(ctx, p, X, Z, ell);
     p.d_state = ctx->get_t<PairState>("state", B);
     ctx->upload(p.d_state, st.data(), sizeof(PairState) * B);
+    build_views(ctx, p, X, Z, ell);
     p.d_ac = ctx->get_t<AlignConst>("aconst", B);
     ctx->upload(p.d_ac, ac.data(), sizeof(AlignConst) * B);
     p.nblk = reduce_blocks(p.clus.desc);
@@ -666,7 +764,7 @@ void setup_problem(cvo_context *ctx, Problem &p, const std::vector<CloudPtrs> &X
 
 void enqueue_iteration(cvo_context *ctx, Problem &p, int mode, double *trace, long long trace_rows, bool timed)
 {
-    PairPassArgs a = pass_args(p.clus, p.grid, p.d_state, 0, p.sig2, p.kappa, p.mom);
+    PairPassArgs a = pass_args(p.clus, p.grid, p.d_state, 0, p.sig2, p.kappa, p.mom, p.plan);
     if (timed) run_pair_pass(ctx, a, p.lay, 0);
     else {
         if (!launch_pair_pass(a, p.lay, 0, ctx->stream))
@@ -677,6 +775,8 @@ void enqueue_iteration(cvo_context *ctx, Problem &p, int mode, double *trace, lo
     std::memset(&r, 0, sizeof(r));
     r.qpts = p.clus.pts;
     r.cdesc = p.clus.d_desc;
+    r.map = slot_map(p.clus, p.plan);
+    r.ticket = p.plan.ticket;
     r.W = p.mom.W;
     r.D = p.mom.D;
     r.S = p.mom.S;
@@ -715,11 +815,13 @@ AlignConst const_for(const cvo_align_params *ap, long long N, long long M)
         a.step_lambda = ap->step_lambda;
         a.max_iter = ap->max_iter;
         a.fixed_iters = ap->fixed_iters;
+        a.metric = ap->metric;
     } else {
         a.max_iter = 1;
         a.step_lambda = 1.0;
     }
     a.sqrt_nm = std::sqrt((double)N * (double)M);
+    a.inv_m = M > 0 ? 1.0 / (double)M : 0.0;
     return a;
 }
 
@@ -735,6 +837,7 @@ void check_align_params(const cvo_align_params *ap)
     require(std::isfinite(ap->sigma) && ap->sigma > 0.0, "sigma must be > 0");
     require(!std::isnan(ap->kappa) && ap->kappa > 0.0, "kappa must be > 0");
     require(ap->max_iter >= 1, "max_iter must be >= 1");
+    require(ap->metric == CVO_METRIC_KINETIC || ap->metric == CVO_METRIC_IDENTITY, "unknown metric");
 }
 
 // single forward evaluation
@@ -778,6 +881,7 @@ template <class F> cvo_status guarded(cvo_context *ctx, F &&f)
     ctx->err.clear();
     try {
         HIP_OK(hipSetDevice(ctx->device));
+        (void)hipGetLastError();  // drop any error left by an earlier failure
         f();
         return CVO_OK;
     } catch (const CvoError &e) {
@@ -825,9 +929,16 @@ void align_many(cvo_context *ctx, const std::vector<CloudPtrs> &X, const std::ve
             if (!ctx->graph || ctx->graph_key != key) {
                 if (ctx->graph) HIP_OK(hipGraphExecDestroy(ctx->graph));
                 ctx->graph = nullptr;
-                hipGraph_t g;
+                hipGraph_t g = nullptr;
                 HIP_OK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-                for (int u = 0; u < U; ++u) enqueue_iteration(ctx, p, 1, d_trace, trace_rows, false);
+                try {
+                    for (int u = 0; u < U; ++u) enqueue_iteration(ctx, p, 1, d_trace, trace_rows, false);
+                } catch (...) {
+                    hipStreamEndCapture(ctx->stream, &g);
+                    if (g) hipGraphDestroy(g);
+                    (void)hipGetLastError();
+                    throw;
+                }
                 HIP_OK(hipStreamEndCapture(ctx->stream, &g));
                 HIP_OK(hipGraphInstantiate(&ctx->graph, g, nullptr, nullptr, 0));
                 HIP_OK(hipGraphDestroy(g));
@@ -1018,8 +1129,20 @@ cvo_status cvo_align_batched(cvo_handle h, int32_t B, const cvo_cloud *X, const 
             xs[b] = to_ptrs(&X[b]);
             zs[b] = to_ptrs(&Z[b]);
         }
+        // the whole batched call runs on the library's own stream, ordered
+        // after everything already enqueued on the caller's stream
         std::vector<PairState> fin;
-        align_many(h, xs, zs, spec, prm, T0, fin, nullptr, true);
+        hipStream_t user = h->stream;
+        HIP_OK(hipStreamSynchronize(user));
+        h->stream = h->capture_stream();
+        try {
+            align_many(h, xs, zs, spec, prm, T0, fin, nullptr, true);
+        } catch (...) {
+            h->stream = user;
+            throw;
+        }
+        HIP_OK(hipStreamSynchronize(h->stream));
+        h->stream = user;
         for (int b = 0; b < B; ++b) {
             std::memcpy(T_out + 12 * b, fin[b].T, sizeof(double) * 12);
             fill_report(fin[b], &reports[b]);
@@ -1059,11 +1182,13 @@ cvo_status cvo_inner_product_backward(cvo_handle h, const cvo_cloud *X, const cv
         if (dZ || dV || dEll) {
             GridView gx = build_grid(h, "fx", {to_ptrs(X)}, {rc}, lay);
             ClusterView cz = build_clusters(h, "fz", {to_ptrs(Z)}, {rc}, lay);
-            Moments m = moments(h, "bm", cz.ntot, lay.d4, true);
-            PairPassArgs a = pass_args(cz, gx, d_state, 0, lay.sig2, kp->kappa, m);
+            Plan pl = make_plan(h, "bp", cz, gx, d_state, 0, kp->kappa);
+            Moments m = moments(h, "bm", pl.nslots, lay.d4, true);
+            PairPassArgs a = pass_args(cz, gx, d_state, 0, lay.sig2, kp->kappa, m, pl);
             run_pair_pass(h, a, lay, 1);
             BackwardArgs ba;
             std::memset(&ba, 0, sizeof(ba));
+            ba.map = slot_map(cz, pl);
             ba.qperm = cz.perm;
             ba.D = m.D;
             ba.G = m.G;
@@ -1077,7 +1202,7 @@ cvo_status cvo_inner_product_backward(cvo_handle h, const cvo_cloud *X, const cv
             launch_backward_finish(ba, h->stream);
             if (dEll) {
                 double *d_sum = h->get_t<double>("bsum", 1);
-                launch_sum_doubles(m.L, M, d_sum, h->stream);
+                launch_sum_doubles(m.L, pl.nslots, d_sum, h->stream);
                 double sl = 0.0;
                 h->download(&sl, d_sum, sizeof(double));
                 const double ascale = kLog2e / (2.0 * kp->ell * kp->ell);
@@ -1089,11 +1214,13 @@ cvo_status cvo_inner_product_backward(cvo_handle h, const cvo_cloud *X, const cv
         if (dX || dU) {
             GridView gz = build_grid(h, "rz", {to_ptrs(Z)}, {rc}, lay);
             ClusterView cx = build_clusters(h, "rx", {to_ptrs(X)}, {rc}, lay);
-            Moments m = moments(h, "bm2", cx.ntot, lay.d4, true);
-            PairPassArgs a = pass_args(cx, gz, d_state, 1, lay.sig2, kp->kappa, m);
+            Plan pl = make_plan(h, "bq", cx, gz, d_state, 1, kp->kappa);
+            Moments m = moments(h, "bm2", pl.nslots, lay.d4, true);
+            PairPassArgs a = pass_args(cx, gz, d_state, 1, lay.sig2, kp->kappa, m, pl);
             run_pair_pass(h, a, lay, 1);
             BackwardArgs ba;
             std::memset(&ba, 0, sizeof(ba));
+            ba.map = slot_map(cx, pl);
             ba.qperm = cx.perm;
             ba.D = m.D;
             ba.G = m.G;
@@ -1129,6 +1256,7 @@ cvo_status cvo_set_tuning(cvo_handle h, const cvo_tuning *in)
         require(in->cluster_factor >= 0.05 && in->cluster_factor <= 2.0, "cluster_factor out of [0.05, 2]");
         require(in->rebuild_ratio > 0.0 && in->rebuild_ratio <= 1.0, "rebuild_ratio out of (0, 1]");
         require(in->unroll >= 1 && in->unroll <= 64, "unroll out of [1, 64]");
+        require(in->piece_work >= 256 && in->piece_work <= (1 << 24), "piece_work out of [256, 2^24]");
         h->tuning = *in;
     });
 }
@@ -1185,10 +1313,11 @@ cvo_status cvo_autotune(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z, co
                 PairState s0 = init_state(T, kp->ell);
                 AlignConst ac = const_for(nullptr, X->n, Z->n);
                 setup_problem(h, p, {to_ptrs(X)}, {to_ptrs(Z)}, {s0}, {ac});
-                PairPassArgs a = pass_args(p.clus, p.grid, p.d_state, 0, p.sig2, p.kappa, p.mom);
+                PairPassArgs a = pass_args(p.clus, p.grid, p.d_state, 0, p.sig2, p.kappa, p.mom, p.plan);
                 hipEvent_t e0 = h->event(), e1 = h->event();
                 std::vector<float> ms;
                 for (int rep = 0; rep < 4; ++rep) {
+                    HIP_OK(hipMemsetAsync(p.plan.ticket, 0, sizeof(unsigned int), h->stream));
                     HIP_OK(hipEventRecord(e0, h->stream));
                     if (!launch_pair_pass(a, p.lay, 0, h->stream))
                         throw CvoError(CVO_ERR_UNSUPPORTED, "no compiled pair kernel for the feature layout");

@@ -376,7 +376,7 @@ __global__ void cluster_heads(const unsigned long long *keys, long long ntot, co
 
 __global__ void cluster_emit(const int *head, const int *hidx, const int2 *span, const float4 *pts,
                              const unsigned long long *keys, int cshift, long long ntot, int2 *clus,
-                             double4 *cgeo, int *cpair)
+                             double4 *cgeo, int *cpair, int *tclus)
 {
     for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < ntot;
          p += (long long)gridDim.x * blockDim.x) {
@@ -402,6 +402,7 @@ __global__ void cluster_emit(const int *head, const int *hidx, const int2 *span,
         clus[idx] = sp;
         cgeo[idx] = make_double4(cc[0], cc[1], cc[2], r);
         cpair[idx] = (int)(keys[p] >> cshift);
+        for (int k = 0; k < sp.y; ++k) tclus[sp.x + k] = idx;
     }
 }
 
@@ -457,10 +458,10 @@ void launch_cluster_heads(const unsigned long long *keys, long long ntot, const 
 
 void launch_cluster_emit(const int *head, const int *hidx, const int2 *span, const float4 *pts,
                          const unsigned long long *keys, int cshift, long long ntot, int2 *clus, double4 *cgeo,
-                         int *cpair, hipStream_t s)
+                         int *cpair, int *tclus, hipStream_t s)
 {
     hipLaunchKernelGGL(cluster_emit, dim3(blocks_for(ntot, 256)), dim3(256), 0, s, head, hidx, span, pts, keys,
-                       cshift, ntot, clus, cgeo, cpair);
+                       cshift, ntot, clus, cgeo, cpair, tclus);
 }
 
 }  // namespace cvo

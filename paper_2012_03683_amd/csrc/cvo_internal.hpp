@@ -25,10 +25,10 @@ namespace cvo {
 
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
-constexpr int kQueueCap = 128;   // LDS candidate queue per wave
-constexpr int kQueueFlush = 64;  // process the queue once it holds this many
+constexpr int kQueueCap = 80;    // LDS candidate queue per wave
+constexpr int kQueueFlush = 16;  // process the queue once it holds this many (cap >= flush + 64)
 constexpr int kTraceLen = 8;
-constexpr int kRedVals = 32;     // values reduced per pair by the reduction kernel
+constexpr int kRedVals = 40;     // values reduced per pair by the reduction kernel
 constexpr int kRedThreads = 256;
 
 enum Status { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAX_ITER = 2, ST_NO_OVERLAP = 3, ST_STATIONARY = 4 };
@@ -52,9 +52,10 @@ struct alignas(16) PairState {
 struct alignas(16) AlignConst {
     double ell_min, decay, ind_rel_tol, eps_rot, eps_trans, step_lambda;
     double sqrt_nm;      // sqrt(|X| |Z|)
+    double inv_m;        // 1 / |Z|
     long long max_iter;
     int fixed_iters;
-    int pad;
+    int metric;          // 0: kinetic-energy metric of the moving cloud, 1: identity
 };
 
 // Uniform grid of one cloud (reference role).
@@ -85,7 +86,10 @@ struct FeatLayout {
     float sig2;        // sigma^2 * prod_b sigma_b^2 over SE blocks
 };
 
-// Arguments of the pair pass.
+// Arguments of the pair pass.  The unit of work is a piece: a contiguous
+// range [c0, c1) of one cluster's candidate list (the concatenation of its
+// neighbourhood rows), planned so that heavy clusters are split.  Persistent
+// waves take pieces heavy-first from an atomic ticket.
 struct PairPassArgs {
     // query side (cluster view)
     const float4 *qpts;
@@ -94,6 +98,10 @@ struct PairPassArgs {
     const double4 *cgeo;  // (centre xyz in the query frame, radius)
     const int *cpair;     // pair of each cluster
     int nclus;
+    const int4 *pieces;   // (cluster, c0, c1, first output slot), cluster-major
+    const int *porder;    // processing order of the pieces (heaviest first)
+    int npieces;
+    unsigned int *ticket; // zero before the launch
     // reference side (grid view)
     const float4 *rpts;
     const float *rfeat;
@@ -105,7 +113,7 @@ struct PairPassArgs {
     int pose_is_inverse;    // 0: query = Z (pose T); 1: query = X (pose T^-1)
     float sig2;
     double kappa;           // +inf: no cutoff
-    // outputs, indexed by the query's sorted position
+    // outputs, indexed by piece slot + position of the query in its cluster
     double *oW;
     double *oD;     // 3 per query
     float *oS;      // 6 per query (forward mode)

@@ -36,15 +36,33 @@ void launch_cluster_heads(const unsigned long long *keys, long long ntot, const 
                           int *head, int2 *span, hipStream_t s);
 void launch_cluster_emit(const int *head, const int *hidx, const int2 *span, const float4 *pts,
                          const unsigned long long *keys, int cshift, long long ntot, int2 *clus, double4 *cgeo,
-                         int *cpair, hipStream_t s);
+                         int *cpair, int *tclus, hipStream_t s);
 
 // pair pass: mode 0 = forward moments, 1 = backward (feature gradients)
 // returns false when no kernel exists for the feature layout
 bool launch_pair_pass(const PairPassArgs &a, const FeatLayout &lay, int mode, hipStream_t s);
+void launch_plan_count(const PairPassArgs &a, int work, int *npieces, int *cmax, long long *ccount, hipStream_t s);
+void launch_plan_emit(const PairPassArgs &a, const int *npieces, const int *pbase, const int *cmax,
+                      const long long *ccount, int4 *pieces, int *pn, unsigned long long *key, int *val,
+                      int2 *cpieces, hipStream_t s);
+void launch_plan_slots(int4 *pieces, const int *tbase, int npieces, hipStream_t s);
+
+// Where a query's partial moments live: query j belongs to cluster tclus[j]
+// at position t = j - clus[c].x; that cluster's pieces are
+// [cpieces[c].x, cpieces[c].x + cpieces[c].y) and piece i keeps the query's
+// partial at slot pieces[i].w + t.  Partials are combined in piece order.
+struct SlotMap {
+    const int *tclus;
+    const int2 *clus;
+    const int2 *cpieces;
+    const int4 *pieces;
+};
 
 struct ReduceArgs {
     const float4 *qpts;
     const ClusterDesc *cdesc;  // per pair: query points [pt_base, pt_base + n)
+    SlotMap map;
+    unsigned int *ticket;      // pair-pass ticket, reset here for the next pass
     const double *W;
     const double *D;
     const float *S;
@@ -62,6 +80,7 @@ void launch_reduce(const ReduceArgs &a, int B, hipStream_t s);
 
 // backward post-processing
 struct BackwardArgs {
+    SlotMap map;
     const int *qperm;         // sorted query index -> original index within its cloud
     const double *D;          // 3 per sorted query (scaled units)
     const double *G;          // d4 per sorted query

@@ -29,6 +29,8 @@
 //     moments.
 #include "cvo_launch.hpp"
 
+#include <algorithm>
+
 namespace cvo {
 
 __device__ __forceinline__ void wave_sync()
@@ -74,8 +76,41 @@ __device__ __forceinline__ bool axis_range(double c, double R, double o, double 
     return true;
 }
 
+// Geometry shared by the planner and the pass: the cluster centre in the
+// reference frame, the cull radius, and the cell ranges of its neighbourhood.
+struct Neighbourhood {
+    double cx, cy, cz, Rm;
+    int ix0, ix1, iy0, iy1, iz0, iz1;
+    bool any;
+};
+
+__device__ __forceinline__ Neighbourhood neighbourhood(const double *Pm, const double4 g, double rc, bool cut,
+                                                       const GridDesc &gd)
+{
+    Neighbourhood nb;
+    nb.cx = Pm[0] * g.x + Pm[1] * g.y + Pm[2] * g.z + Pm[3];
+    nb.cy = Pm[4] * g.x + Pm[5] * g.y + Pm[6] * g.z + Pm[7];
+    nb.cz = Pm[8] * g.x + Pm[9] * g.y + Pm[10] * g.z + Pm[11];
+    nb.Rm = cut ? (rc + g.w) * (1.0 + 1e-5) : INFINITY;
+    nb.ix0 = 0; nb.ix1 = gd.nx - 1; nb.iy0 = 0; nb.iy1 = gd.ny - 1; nb.iz0 = 0; nb.iz1 = gd.nz - 1;
+    nb.any = gd.n > 0;
+    if (cut && nb.any)
+        nb.any = axis_range(nb.cx, nb.Rm, gd.ox, gd.h, gd.nx, nb.ix0, nb.ix1) &&
+                 axis_range(nb.cy, nb.Rm, gd.oy, gd.h, gd.ny, nb.iy0, nb.iy1) &&
+                 axis_range(nb.cz, nb.Rm, gd.oz, gd.h, gd.nz, nb.iz0, nb.iz1);
+    return nb;
+}
+
+template <int SED, int LIND, int MODE> struct PassTraits {
+    static constexpr int D = SED + LIND;
+    static constexpr int D4 = (D + 3) & ~3;
+    // waves per SIMD the register budget is sized for (no spills)
+    static constexpr int kMinWaves = (MODE == 0 && D4 <= 24) ? 3 : 2;
+};
+
 template <int SED, int LIND, int MODE>
-__global__ __launch_bounds__(kWave * kWavesPerBlock) void pair_pass_kernel(const PairPassArgs a)
+__global__ __launch_bounds__(kWave * kWavesPerBlock, (PassTraits<SED, LIND, MODE>::kMinWaves))
+void pair_pass_kernel(const PairPassArgs a)
 {
     constexpr int D = SED + LIND;
     constexpr int D4 = (D + 3) & ~3;
@@ -90,131 +125,100 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void pair_pass_kernel(const
 
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
-    const int c = wave_uniform(blockIdx.x * kWavesPerBlock + wv);
-    if (c >= a.nclus) return;
-    const int b = wave_uniform(a.cpair[c]);
-    const PairState *st = a.state + b;
-    if (st->done) return;
-
-    const double *P = a.pose_is_inverse ? st->Tinv : st->T;
-    double Pm[12];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) Pm[k] = P[k];
-    const double ell = st->ell;
-    const double ascale = 1.4426950408889634 / (2.0 * ell * ell);  // log2(e) / (2 ell^2)
-    const double sc = sqrt(ascale);
-    const bool cut = isfinite(a.kappa);
-    const double rc = a.kappa * ell;
-    const double rc2 = rc * rc;
-
-    const int2 cl = a.clus[c];
-    const double4 g = a.cgeo[c];
-    const double cx = Pm[0] * g.x + Pm[1] * g.y + Pm[2] * g.z + Pm[3];
-    const double cy = Pm[4] * g.x + Pm[5] * g.y + Pm[6] * g.z + Pm[7];
-    const double cz = Pm[8] * g.x + Pm[9] * g.y + Pm[10] * g.z + Pm[11];
-    const double rho = g.w;
-
-    // thresholds in scaled units: s' <= lo is certainly in P, s' > hi is
-    // certainly out; between them the FP64 definition decides.  The band is
-    // 8x the worst-case FP32 error 2^-24 (4 (1 + rho/rc) + 3) a rc^2 plus
-    // the rounding of the thresholds themselves.
-    float hi = INFINITY, lo = INFINITY, cull2 = INFINITY;
-    double Rm = INFINITY;
-    if (cut) {
-        const double u = 5.9604644775390625e-8;
-        const double G = u * (8.0 * (4.0 * (1.0 + rho / rc) + 3.0) + 4.0);
-        const double r2s = rc2 * ascale;
-        hi = (float)(r2s * (1.0 + G));
-        lo = (float)(r2s * (1.0 - G));
-        Rm = (rc + rho) * (1.0 + 1e-5);
-        cull2 = (float)(Rm * Rm * ascale);
-    }
-
-    // query point owned by this lane
-    const int n = cl.y;
-    const int np2 = (n <= 1) ? 1 : (1 << (32 - __clz(n - 1)));
-    const int lg = __ffs(np2) - 1;
-    const int t = lane & (np2 - 1);
-    const int qs = lane >> lg;
-    const int SUB = kWave >> lg;
-    const bool active = t < n;
-    const int pq = cl.x + (active ? t : 0);
-    const float4 zq = a.qpts[pq];
-    const double zpx = Pm[0] * zq.x + Pm[1] * zq.y + Pm[2] * zq.z + Pm[3];
-    const double zpy = Pm[4] * zq.x + Pm[5] * zq.y + Pm[6] * zq.z + Pm[7];
-    const double zpz = Pm[8] * zq.x + Pm[9] * zq.y + Pm[10] * zq.z + Pm[11];
-    const float zrx = (float)((zpx - cx) * sc);
-    const float zry = (float)((zpy - cy) * sc);
-    const float zrz = (float)((zpz - cz) * sc);
-    float vf[VF];
-#pragma unroll
-    for (int f = 0; f < F4; ++f) {
-        const float4 v4 = reinterpret_cast<const float4 *>(a.qfeat)[(long long)pq * F4 + f];
-        vf[4 * f + 0] = v4.x;
-        vf[4 * f + 1] = v4.y;
-        vf[4 * f + 2] = v4.z;
-        vf[4 * f + 3] = v4.w;
-    }
-
-    double W = 0.0, Dx = 0.0, Dy = 0.0, Dz = 0.0;
-    float S00 = 0.f, S01 = 0.f, S02 = 0.f, S11 = 0.f, S12 = 0.f, S22 = 0.f;
-    int cnt = 0;
-    double Gf[MODE == 1 ? VF : 1];
-    double Ls = 0.0;
-#pragma unroll
-    for (int k = 0; k < (MODE == 1 ? VF : 1); ++k) Gf[k] = 0.0;
-
-    const float sig2 = a.sig2;
     const unsigned long long lt_mask = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
+    const float sig2 = a.sig2;
+    const bool cut = isfinite(a.kappa);
 
-    auto process = [&](int qn) {
-        for (int k = qs; k < qn; k += SUB) {
-            const float4 e = s_xyz[wv][k];
-            const float dx = e.x - zrx, dy = e.y - zry, dz = e.z - zrz;
-            const float s = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-            if (active && s <= hi) {
-                bool pass = true;
-                if (s > lo) {
-                    const float4 rp = a.rpts[s_src[wv][k]];
-                    pass = a.pose_is_inverse
-                               ? canonical_member(st->T, zq.x, zq.y, zq.z, rp.x, rp.y, rp.z, rc2)
-                               : canonical_member(st->T, rp.x, rp.y, rp.z, zq.x, zq.y, zq.z, rc2);
-                }
-                if (pass) {
-                    float E = s;
-                    float lin = 0.0f;
+    for (;;) {
+        int tk = 0;
+        if (lane == 0) tk = (int)atomicAdd(a.ticket, 1u);
+        tk = wave_uniform(__shfl(tk, 0));
+        if (tk >= a.npieces) break;
+        const int4 pc = a.pieces[a.porder[tk]];
+        const int c = pc.x;
+        const int b = wave_uniform(a.cpair[c]);
+        const PairState *st = a.state + b;
+        if (st->done) continue;
+
+        const double *P = a.pose_is_inverse ? st->Tinv : st->T;
+        double Pm[12];
 #pragma unroll
-                    for (int f = 0; f < F4; ++f) {
-                        const float4 u4 = s_ft[wv][k * F4 + f];
-                        const float uu[4] = {u4.x, u4.y, u4.z, u4.w};
+        for (int k = 0; k < 12; ++k) Pm[k] = P[k];
+        const double ell = st->ell;
+        const double ascale = 1.4426950408889634 / (2.0 * ell * ell);  // log2(e) / (2 ell^2)
+        const double sc = sqrt(ascale);
+        const double rc = a.kappa * ell;
+        const double rc2 = rc * rc;
+        const int2 cl = a.clus[c];
+        const double4 g = a.cgeo[c];
+        const GridDesc gd = a.grids[b];
+        const Neighbourhood nb = neighbourhood(Pm, g, rc, cut, gd);
+        const double cx = nb.cx, cy = nb.cy, cz = nb.cz;
+
+        // thresholds in scaled units: s' <= lo is certainly in P, s' > hi is
+        // certainly out; between them the FP64 definition decides.  The band
+        // is 8x the worst-case FP32 error 2^-24 (4 (1 + rho/rc) + 3) a rc^2
+        // plus the rounding of the thresholds themselves.
+        float hi = INFINITY, lo = INFINITY, cull2 = INFINITY;
+        if (cut) {
+            const double u = 5.9604644775390625e-8;
+            const double G = u * (8.0 * (4.0 * (1.0 + g.w / rc) + 3.0) + 4.0);
+            const double r2s = rc2 * ascale;
+            hi = (float)(r2s * (1.0 + G));
+            lo = (float)(r2s * (1.0 - G));
+            cull2 = (float)(nb.Rm * nb.Rm * ascale);
+        }
+
+        // query point owned by this lane; SUB sub-streams share the candidates
+        const int n = cl.y;
+        const int np2 = (n <= 1) ? 1 : (1 << (32 - __clz(n - 1)));
+        const int lg = __ffs(np2) - 1;
+        const int t = lane & (np2 - 1);
+        const int qs = lane >> lg;
+        const int SUB = kWave >> lg;
+        const bool active = t < n;
+        const int pq = cl.x + (active ? t : 0);
+        const float4 zq = a.qpts[pq];
+        const double zpx = Pm[0] * zq.x + Pm[1] * zq.y + Pm[2] * zq.z + Pm[3];
+        const double zpy = Pm[4] * zq.x + Pm[5] * zq.y + Pm[6] * zq.z + Pm[7];
+        const double zpz = Pm[8] * zq.x + Pm[9] * zq.y + Pm[10] * zq.z + Pm[11];
+        const float zrx = (float)((zpx - cx) * sc);
+        const float zry = (float)((zpy - cy) * sc);
+        const float zrz = (float)((zpz - cz) * sc);
+        float vf[VF];
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const int d = 4 * f + q;
-                            if (d < SED) {
-                                const float df = uu[q] - vf[d];
-                                E = fmaf(df, df, E);
-                            } else if (d < D) {
-                                lin = fmaf(uu[q], vf[d], lin);
-                            }
-                        }
+        for (int f = 0; f < F4; ++f) {
+            const float4 v4 = reinterpret_cast<const float4 *>(a.qfeat)[(long long)pq * F4 + f];
+            vf[4 * f + 0] = v4.x;
+            vf[4 * f + 1] = v4.y;
+            vf[4 * f + 2] = v4.z;
+            vf[4 * f + 3] = v4.w;
+        }
+
+        double W = 0.0, Dx = 0.0, Dy = 0.0, Dz = 0.0;
+        float S00 = 0.f, S01 = 0.f, S02 = 0.f, S11 = 0.f, S12 = 0.f, S22 = 0.f;
+        int cnt = 0;
+        double Gf[MODE == 1 ? VF : 1];
+        double Ls = 0.0;
+#pragma unroll
+        for (int k = 0; k < (MODE == 1 ? VF : 1); ++k) Gf[k] = 0.0;
+
+        auto process = [&](int qn) {
+            for (int k = qs; k < qn; k += SUB) {
+                const float4 e = s_xyz[wv][k];
+                const float dx = e.x - zrx, dy = e.y - zry, dz = e.z - zrz;
+                const float s = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                if (active && s <= hi) {
+                    bool pass = true;
+                    if (s > lo) {
+                        const float4 rp = a.rpts[s_src[wv][k]];
+                        pass = a.pose_is_inverse
+                                   ? canonical_member(st->T, zq.x, zq.y, zq.z, rp.x, rp.y, rp.z, rc2)
+                                   : canonical_member(st->T, rp.x, rp.y, rp.z, zq.x, zq.y, zq.z, rc2);
                     }
-                    const float wnl = sig2 * __builtin_amdgcn_exp2f(-E);
-                    const float w = (LIND > 0) ? wnl * lin : wnl;
-                    W += (double)w;
-                    const float wx = w * dx, wy = w * dy, wz = w * dz;
-                    Dx += (double)wx;
-                    Dy += (double)wy;
-                    Dz += (double)wz;
-                    cnt += 1;
-                    if (MODE == 0) {
-                        S00 = fmaf(wx, dx, S00);
-                        S01 = fmaf(wx, dy, S01);
-                        S02 = fmaf(wx, dz, S02);
-                        S11 = fmaf(wy, dy, S11);
-                        S12 = fmaf(wy, dz, S12);
-                        S22 = fmaf(wz, dz, S22);
-                    } else {
-                        Ls += (double)(w * s);
+                    if (pass) {
+                        float E = s;
+                        float lin = 0.0f;
 #pragma unroll
                         for (int f = 0; f < F4; ++f) {
                             const float4 u4 = s_ft[wv][k * F4 + f];
@@ -222,123 +226,245 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void pair_pass_kernel(const
 #pragma unroll
                             for (int q = 0; q < 4; ++q) {
                                 const int d = 4 * f + q;
-                                if (MODE == 1 && d < SED) Gf[d] += (double)(w * (uu[q] - vf[d]));
-                                else if (MODE == 1 && d < D) Gf[d] += (double)(wnl * uu[q]);
+                                if (d < SED) {
+                                    const float df = uu[q] - vf[d];
+                                    E = fmaf(df, df, E);
+                                } else if (d < D) {
+                                    lin = fmaf(uu[q], vf[d], lin);
+                                }
+                            }
+                        }
+                        const float wnl = sig2 * __builtin_amdgcn_exp2f(-E);
+                        const float w = (LIND > 0) ? wnl * lin : wnl;
+                        W += (double)w;
+                        const float wx = w * dx, wy = w * dy, wz = w * dz;
+                        Dx += (double)wx;
+                        Dy += (double)wy;
+                        Dz += (double)wz;
+                        cnt += 1;
+                        if (MODE == 0) {
+                            S00 = fmaf(wx, dx, S00);
+                            S01 = fmaf(wx, dy, S01);
+                            S02 = fmaf(wx, dz, S02);
+                            S11 = fmaf(wy, dy, S11);
+                            S12 = fmaf(wy, dz, S12);
+                            S22 = fmaf(wz, dz, S22);
+                        } else {
+                            Ls += (double)(w * s);
+#pragma unroll
+                            for (int f = 0; f < F4; ++f) {
+                                const float4 u4 = s_ft[wv][k * F4 + f];
+                                const float uu[4] = {u4.x, u4.y, u4.z, u4.w};
+#pragma unroll
+                                for (int q = 0; q < 4; ++q) {
+                                    const int d = 4 * f + q;
+                                    if (MODE == 1 && d < SED) Gf[d] += (double)(w * (uu[q] - vf[d]));
+                                    else if (MODE == 1 && d < D) Gf[d] += (double)(wnl * uu[q]);
+                                }
                             }
                         }
                     }
                 }
             }
-        }
-    };
+        };
 
-    const GridDesc gd = a.grids[b];
-    int ix0 = 0, ix1 = gd.nx - 1, iy0 = 0, iy1 = gd.ny - 1, iz0 = 0, iz1 = gd.nz - 1;
-    bool any = gd.n > 0;
-    if (cut && any) {
-        any = axis_range(cx, Rm, gd.ox, gd.h, gd.nx, ix0, ix1) && axis_range(cy, Rm, gd.oy, gd.h, gd.ny, iy0, iy1) &&
-              axis_range(cz, Rm, gd.oz, gd.h, gd.nz, iz0, iz1);
-    }
-    int qn = 0;
-    if (any) {
-        const int nyr = iy1 - iy0 + 1;
-        const int nrows = nyr * (iz1 - iz0 + 1);
-        const int run = ix1 - ix0 + 1;
-        for (int rb = 0; rb < nrows; rb += kWave) {
-            const int r = rb + lane;
-            int rs = 0, len = 0;
-            if (r < nrows) {
-                const int iy = iy0 + r % nyr, iz = iz0 + r / nyr;
-                const long long k0 =
-                    (long long)gd.cell_base + ix0 + (long long)gd.nx * (iy + (long long)gd.ny * iz);
-                rs = a.cell_start[k0];
-                len = a.cell_start[k0 + run] - rs;
-            }
-            int incl = len;
+        // this piece covers candidates [c0, c1) of the concatenated rows
+        const int c0 = pc.y, c1 = pc.z;
+        int qn = 0;
+        if (nb.any) {
+            const int nyr = nb.iy1 - nb.iy0 + 1;
+            const int nrows = nyr * (nb.iz1 - nb.iz0 + 1);
+            const int run = nb.ix1 - nb.ix0 + 1;
+            int base = 0;  // candidates in earlier row batches
+            for (int rb = 0; rb < nrows && base < c1; rb += kWave) {
+                const int r = rb + lane;
+                int rs = 0, len = 0;
+                if (r < nrows) {
+                    const int iy = nb.iy0 + r % nyr, iz = nb.iz0 + r / nyr;
+                    const long long k0 =
+                        (long long)gd.cell_base + nb.ix0 + (long long)gd.nx * (iy + (long long)gd.ny * iz);
+                    rs = a.cell_start[k0];
+                    len = a.cell_start[k0 + run] - rs;
+                }
+                int incl = len;
 #pragma unroll
-            for (int off = 1; off < kWave; off <<= 1) {
-                const int v = __shfl_up(incl, off);
-                if (lane >= off) incl += v;
-            }
-            const int total = __shfl(incl, kWave - 1);
-            s_rs[wv][lane] = rs;
-            s_rx[wv][lane] = incl - len;
-            wave_sync();
-            for (int m0 = 0; m0 < total; m0 += kWave) {
-                const int m = m0 + lane;
-                bool keep = false;
-                int src = 0;
-                float x0 = 0.f, x1 = 0.f, x2 = 0.f;
-                if (m < total) {
-                    int lo_ = 0, hi_ = kWave - 1;
-                    while (lo_ < hi_) {
-                        const int mid = (lo_ + hi_ + 1) >> 1;
-                        if (s_rx[wv][mid] <= m) lo_ = mid; else hi_ = mid - 1;
+                for (int off = 1; off < kWave; off <<= 1) {
+                    const int v = __shfl_up(incl, off);
+                    if (lane >= off) incl += v;
+                }
+                const int total = __shfl(incl, kWave - 1);
+                const int m_lo = max(c0 - base, 0);
+                const int m_hi = min(c1 - base, total);
+                if (m_lo < m_hi) {
+                    s_rs[wv][lane] = rs;
+                    s_rx[wv][lane] = incl - len;
+                    wave_sync();
+                    for (int m0 = m_lo; m0 < m_hi; m0 += kWave) {
+                        const int m = m0 + lane;
+                        bool keep = false;
+                        int src = 0;
+                        float x0 = 0.f, x1 = 0.f, x2 = 0.f;
+                        if (m < m_hi) {
+                            int lo_ = 0, hi_ = kWave - 1;
+                            while (lo_ < hi_) {
+                                const int mid = (lo_ + hi_ + 1) >> 1;
+                                if (s_rx[wv][mid] <= m) lo_ = mid; else hi_ = mid - 1;
+                            }
+                            src = s_rs[wv][lo_] + (m - s_rx[wv][lo_]);
+                            const float4 xp = a.rpts[src];
+                            x0 = (float)(((double)xp.x - cx) * sc);
+                            x1 = (float)(((double)xp.y - cy) * sc);
+                            x2 = (float)(((double)xp.z - cz) * sc);
+                            keep = fmaf(x2, x2, fmaf(x1, x1, x0 * x0)) <= cull2;
+                        }
+                        const unsigned long long mask = __ballot(keep);
+                        if (keep) {
+                            const int slot = qn + __popcll(mask & lt_mask);
+                            s_xyz[wv][slot] = make_float4(x0, x1, x2, 0.0f);
+                            s_src[wv][slot] = src;
+                            const float4 *fr = reinterpret_cast<const float4 *>(a.rfeat) + (long long)src * F4;
+#pragma unroll
+                            for (int f = 0; f < F4; ++f) s_ft[wv][slot * F4 + f] = fr[f];
+                        }
+                        qn += __popcll(mask);
+                        wave_sync();
+                        if (qn >= kQueueFlush) {
+                            process(qn);
+                            qn = 0;
+                            wave_sync();
+                        }
                     }
-                    src = s_rs[wv][lo_] + (m - s_rx[wv][lo_]);
-                    const float4 xp = a.rpts[src];
-                    x0 = (float)(((double)xp.x - cx) * sc);
-                    x1 = (float)(((double)xp.y - cy) * sc);
-                    x2 = (float)(((double)xp.z - cz) * sc);
-                    keep = fmaf(x2, x2, fmaf(x1, x1, x0 * x0)) <= cull2;
-                }
-                const unsigned long long mask = __ballot(keep);
-                if (keep) {
-                    const int slot = qn + __popcll(mask & lt_mask);
-                    s_xyz[wv][slot] = make_float4(x0, x1, x2, 0.0f);
-                    s_src[wv][slot] = src;
-                    const float4 *fr = reinterpret_cast<const float4 *>(a.rfeat) + (long long)src * F4;
-#pragma unroll
-                    for (int f = 0; f < F4; ++f) s_ft[wv][slot * F4 + f] = fr[f];
-                }
-                qn += __popcll(mask);
-                wave_sync();
-                if (qn >= kQueueFlush) {
-                    process(qn);
-                    qn = 0;
                     wave_sync();
                 }
+                base += total;
             }
-            wave_sync();
         }
-    }
-    process(qn);
+        process(qn);
+        wave_sync();
 
-    // combine the sub-streams of each query (fixed shuffle order)
-    for (int off = np2; off < kWave; off <<= 1) {
-        W += __shfl_xor(W, off);
-        Dx += __shfl_xor(Dx, off);
-        Dy += __shfl_xor(Dy, off);
-        Dz += __shfl_xor(Dz, off);
-        cnt += __shfl_xor(cnt, off);
-        if (MODE == 0) {
-            S00 += __shfl_xor(S00, off);
-            S01 += __shfl_xor(S01, off);
-            S02 += __shfl_xor(S02, off);
-            S11 += __shfl_xor(S11, off);
-            S12 += __shfl_xor(S12, off);
-            S22 += __shfl_xor(S22, off);
-        } else {
-            Ls += __shfl_xor(Ls, off);
+        // combine the sub-streams of each query (fixed shuffle order)
+        for (int off = np2; off < kWave; off <<= 1) {
+            W += __shfl_xor(W, off);
+            Dx += __shfl_xor(Dx, off);
+            Dy += __shfl_xor(Dy, off);
+            Dz += __shfl_xor(Dz, off);
+            cnt += __shfl_xor(cnt, off);
+            if (MODE == 0) {
+                S00 += __shfl_xor(S00, off);
+                S01 += __shfl_xor(S01, off);
+                S02 += __shfl_xor(S02, off);
+                S11 += __shfl_xor(S11, off);
+                S12 += __shfl_xor(S12, off);
+                S22 += __shfl_xor(S22, off);
+            } else {
+                Ls += __shfl_xor(Ls, off);
 #pragma unroll
-            for (int k = 0; k < (MODE == 1 ? VF : 1); ++k) Gf[k] += __shfl_xor(Gf[k], off);
+                for (int k = 0; k < (MODE == 1 ? VF : 1); ++k) Gf[k] += __shfl_xor(Gf[k], off);
+            }
+        }
+        if (qs == 0 && active) {
+            const long long o = (long long)pc.w + t;
+            a.oW[o] = W;
+            a.oD[3 * o + 0] = Dx;
+            a.oD[3 * o + 1] = Dy;
+            a.oD[3 * o + 2] = Dz;
+            a.oCnt[o] = cnt;
+            if (MODE == 0) {
+                float *S = a.oS + 6 * o;
+                S[0] = S00; S[1] = S01; S[2] = S02; S[3] = S11; S[4] = S12; S[5] = S22;
+            } else {
+                a.oL[o] = Ls;
+#pragma unroll
+                for (int k = 0; k < (MODE == 1 ? D4 : 0); ++k) a.oG[o * D4 + k] = Gf[k];
+            }
         }
     }
-    if (qs == 0 && active) {
-        a.oW[pq] = W;
-        a.oD[3 * (long long)pq + 0] = Dx;
-        a.oD[3 * (long long)pq + 1] = Dy;
-        a.oD[3 * (long long)pq + 2] = Dz;
-        a.oCnt[pq] = cnt;
-        if (MODE == 0) {
-            float *S = a.oS + 6 * (long long)pq;
-            S[0] = S00; S[1] = S01; S[2] = S02; S[3] = S11; S[4] = S12; S[5] = S22;
-        } else {
-            a.oL[pq] = Ls;
-#pragma unroll
-            for (int k = 0; k < (MODE == 1 ? D4 : 0); ++k) a.oG[(long long)pq * D4 + k] = Gf[k];
+}
+
+// ---------------------------------------------------------------- planning
+// Per cluster, at the current pose: the number of candidates of its
+// neighbourhood and how many pieces to cut it into (work per piece about
+// `work` query-candidate products, at least 256 candidates per piece).
+__global__ void plan_count(const PairPassArgs a, int work, int *npieces, int *cmax, long long *ccount)
+{
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < a.nclus; c += gridDim.x * blockDim.x) {
+        const int b = a.cpair[c];
+        const PairState *st = a.state + b;
+        const double *P = a.pose_is_inverse ? st->Tinv : st->T;
+        double Pm[12];
+        for (int k = 0; k < 12; ++k) Pm[k] = P[k];
+        const bool cut = isfinite(a.kappa);
+        const double rc = a.kappa * st->ell;
+        const GridDesc gd = a.grids[b];
+        const Neighbourhood nb = neighbourhood(Pm, a.cgeo[c], rc, cut, gd);
+        long long C = 0;
+        if (nb.any) {
+            const int run = nb.ix1 - nb.ix0 + 1;
+            for (int iz = nb.iz0; iz <= nb.iz1; ++iz)
+                for (int iy = nb.iy0; iy <= nb.iy1; ++iy) {
+                    const long long k0 =
+                        (long long)gd.cell_base + nb.ix0 + (long long)gd.nx * (iy + (long long)gd.ny * iz);
+                    C += a.cell_start[k0 + run] - a.cell_start[k0];
+                }
+        }
+        const int n = a.clus[c].y;
+        const int cm = max(256, work / max(n, 1));
+        const long long np = C > 0 ? (C + cm - 1) / cm : 1;
+        npieces[c] = (int)min(np, 4096LL);
+        cmax[c] = cm;
+        ccount[c] = C;
+    }
+}
+
+// Emit the pieces of each cluster (cluster-major), their query counts (for
+// the output-slot scan) and a sort key: the heaviest piece gets the smallest key.
+__global__ void plan_emit(const PairPassArgs a, const int *npieces, const int *pbase, const int *cmax,
+                          const long long *ccount, int4 *pieces, int *pn, unsigned long long *key, int *val,
+                          int2 *cpieces)
+{
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < a.nclus; c += gridDim.x * blockDim.x) {
+        const int np = npieces[c], pb = pbase[c], cm = cmax[c];
+        const int n = a.clus[c].y;
+        const long long C = ccount[c];
+        cpieces[c] = make_int2(pb, np);
+        for (int p = 0; p < np; ++p) {
+            const int c0 = p * cm;
+            const int c1 = (p == np - 1) ? 0x7fffffff : (p + 1) * cm;
+            pieces[pb + p] = make_int4(c, c0, c1, 0);
+            pn[pb + p] = n;
+            const long long cand = (p == np - 1) ? max(C - (long long)c0, 0LL) : (long long)cm;
+            const unsigned long long cost = (unsigned long long)n * (unsigned long long)(cand + 64);
+            key[pb + p] = 0xffffffffULL - (cost > 0xffffffffULL ? 0xffffffffULL : cost);
+            val[pb + p] = pb + p;
         }
     }
+}
+
+__global__ void plan_slots(int4 *pieces, const int *tbase, int npieces)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npieces; i += gridDim.x * blockDim.x)
+        pieces[i].w = tbase[i];
+}
+
+void launch_plan_count(const PairPassArgs &a, int work, int *npieces, int *cmax, long long *ccount, hipStream_t s)
+{
+    const int nb = std::max(1, std::min(4096, (a.nclus + 255) / 256));
+    hipLaunchKernelGGL(plan_count, dim3(nb), dim3(256), 0, s, a, work, npieces, cmax, ccount);
+}
+
+void launch_plan_emit(const PairPassArgs &a, const int *npieces, const int *pbase, const int *cmax,
+                      const long long *ccount, int4 *pieces, int *pn, unsigned long long *key, int *val,
+                      int2 *cpieces, hipStream_t s)
+{
+    const int nb = std::max(1, std::min(4096, (a.nclus + 255) / 256));
+    hipLaunchKernelGGL(plan_emit, dim3(nb), dim3(256), 0, s, a, npieces, pbase, cmax, ccount, pieces, pn, key, val,
+                       cpieces);
+}
+
+void launch_plan_slots(int4 *pieces, const int *tbase, int npieces, hipStream_t s)
+{
+    const int nb = std::max(1, std::min(4096, (npieces + 255) / 256));
+    hipLaunchKernelGGL(plan_slots, dim3(nb), dim3(256), 0, s, pieces, tbase, npieces);
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -358,8 +484,11 @@ bool pair_layout_supported(int sed, int lind)
 
 bool launch_pair_pass(const PairPassArgs &a, const FeatLayout &lay, int mode, hipStream_t s)
 {
-    if (a.nclus <= 0) return true;
-    const dim3 grid((a.nclus + kWavesPerBlock - 1) / kWavesPerBlock);
+    if (a.npieces <= 0) return true;
+    // persistent waves: enough to fill the chip several times over, never
+    // more than there are pieces
+    const int blocks = std::max(1, std::min((a.npieces + kWavesPerBlock - 1) / kWavesPerBlock, 256 * 8));
+    const dim3 grid(blocks);
     const dim3 block(kWave * kWavesPerBlock);
 #define CVO_LAUNCH(S, L)                                                                  \
     if (lay.sed == S && lay.lind == L) {                                                  \

@@ -23,8 +23,58 @@ namespace cvo {
 
 // accumulator slots
 enum {
-    R_F = 0, R_OM = 1, R_V = 4, R_HWW = 7, R_HWV = 13, R_HVV = 22, R_TRS = 28, R_N = 29, R_RMAX = 30
+    R_F = 0, R_OM = 1, R_V = 4, R_HWW = 7, R_HWV = 13, R_HVV = 22, R_TRS = 28, R_N = 29, R_RMAX = 30,
+    R_ZS = 31, R_ZZ = 34, R_END = 40
 };
+
+// Solve A x = b for the 6x6 system (Gaussian elimination, partial pivoting).
+__device__ bool solve6(const double A_in[36], const double b[6], double x[6])
+{
+    double A[6][7];
+    for (int r = 0; r < 6; ++r) {
+        for (int c = 0; c < 6; ++c) A[r][c] = A_in[6 * r + c];
+        A[r][6] = b[r];
+    }
+    for (int c = 0; c < 6; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 6; ++r)
+            if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+        if (A[piv][c] == 0.0) return false;
+        if (piv != c)
+            for (int k = 0; k < 7; ++k) {
+                const double t = A[c][k];
+                A[c][k] = A[piv][k];
+                A[piv][k] = t;
+            }
+        for (int r = c + 1; r < 6; ++r) {
+            const double f = A[r][c] / A[c][c];
+            for (int k = c; k < 7; ++k) A[r][k] -= f * A[c][k];
+        }
+    }
+    for (int r = 5; r >= 0; --r) {
+        double s = A[r][6];
+        for (int k = r + 1; k < 6; ++k) s -= A[r][k] * x[k];
+        x[r] = s / A[r][r];
+    }
+    return true;
+}
+
+// xi^T H xi for the reduced 6x6 curvature matrix
+__device__ double quad_form(const double *tot, const double xi[6])
+{
+    const double Hww[3][3] = {{tot[R_HWW + 0], tot[R_HWW + 1], tot[R_HWW + 2]},
+                              {tot[R_HWW + 1], tot[R_HWW + 3], tot[R_HWW + 4]},
+                              {tot[R_HWW + 2], tot[R_HWW + 4], tot[R_HWW + 5]}};
+    const double Hvv[3][3] = {{tot[R_HVV + 0], tot[R_HVV + 1], tot[R_HVV + 2]},
+                              {tot[R_HVV + 1], tot[R_HVV + 3], tot[R_HVV + 4]},
+                              {tot[R_HVV + 2], tot[R_HVV + 4], tot[R_HVV + 5]}};
+    double q = 0.0;
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k)
+            q += xi[r] * Hww[r][k] * xi[k] + 2.0 * xi[r] * tot[R_HWV + 3 * r + k] * xi[3 + k] +
+                 xi[3 + r] * Hvv[r][k] * xi[3 + k];
+    return q;
+}
 
 // SE(3) exponential of xi = (omega, v): R = I + a W + b W^2, V = I + b W + c W^2,
 // p = V v with a = sin th / th, b = (1 - cos th) / th^2, c = (th - sin th) / th^3,
@@ -90,17 +140,7 @@ __device__ void finalize_pair(PairState *st, const AlignConst *ac, const double 
         g[k] = tot[R_OM + k] * il2;
         g[3 + k] = tot[R_V + k] * il2;
     }
-    const double Hww[3][3] = {{tot[R_HWW + 0], tot[R_HWW + 1], tot[R_HWW + 2]},
-                              {tot[R_HWW + 1], tot[R_HWW + 3], tot[R_HWW + 4]},
-                              {tot[R_HWW + 2], tot[R_HWW + 4], tot[R_HWW + 5]}};
-    const double Hvv[3][3] = {{tot[R_HVV + 0], tot[R_HVV + 1], tot[R_HVV + 2]},
-                              {tot[R_HVV + 1], tot[R_HVV + 3], tot[R_HVV + 4]},
-                              {tot[R_HVV + 2], tot[R_HVV + 4], tot[R_HVV + 5]}};
-    double curv = 0.0;
-    for (int r = 0; r < 3; ++r)
-        for (int k = 0; k < 3; ++k)
-            curv += g[r] * Hww[r][k] * g[k] + 2.0 * g[r] * tot[R_HWV + 3 * r + k] * g[3 + k] +
-                    g[3 + r] * Hvv[r][k] * g[3 + k];
+    const double curv = quad_form(tot, g);
     const double F = tot[R_F];
     const double np = tot[R_N];
     const double ind = (ac->sqrt_nm > 0.0) ? F / ac->sqrt_nm : 0.0;
@@ -118,13 +158,40 @@ __device__ void finalize_pair(PairState *st, const AlignConst *ac, const double 
     // ---- ascent step (same decision sequence as the definition it follows)
     if (np == 0.0) { st->status = ST_NO_OVERLAP; st->done = 1; return; }
     if (gn2 == 0.0) { st->status = ST_STATIONARY; st->done = 1; return; }
-    const double tauN = (curv < 0.0) ? gn2 / (-curv) : INFINITY;
-    const double nw = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
-    const double nv = sqrt(g[3] * g[3] + g[4] * g[4] + g[5] * g[5]);
+    // direction: the Riemannian gradient G^-1 g.  Kinetic-energy metric of
+    // the moving cloud: G = [[tr(S) I - S + mu I, [c]_x], [[c]_x^T, I]] with
+    // c = mean z', S = mean z' z'^T, mu = 1e-6 (tr S + 1e-12).
+    double d[6];
+    if (ac->metric == 0) {
+        const double im = ac->inv_m;
+        const double c[3] = {tot[R_ZS] * im, tot[R_ZS + 1] * im, tot[R_ZS + 2] * im};
+        const double S[3][3] = {{tot[R_ZZ + 0] * im, tot[R_ZZ + 1] * im, tot[R_ZZ + 2] * im},
+                                {tot[R_ZZ + 1] * im, tot[R_ZZ + 3] * im, tot[R_ZZ + 4] * im},
+                                {tot[R_ZZ + 2] * im, tot[R_ZZ + 4] * im, tot[R_ZZ + 5] * im}};
+        const double trs = S[0][0] + S[1][1] + S[2][2];
+        const double mu = 1e-6 * (trs + 1e-12);
+        const double Cx[3][3] = {{0.0, -c[2], c[1]}, {c[2], 0.0, -c[0]}, {-c[1], c[0], 0.0}};
+        double G[36];
+        for (int r = 0; r < 3; ++r)
+            for (int k = 0; k < 3; ++k) {
+                G[6 * r + k] = (r == k ? trs + mu : 0.0) - S[r][k];
+                G[6 * r + 3 + k] = Cx[r][k];
+                G[6 * (3 + r) + k] = Cx[k][r];
+                G[6 * (3 + r) + 3 + k] = (r == k) ? 1.0 : 0.0;
+            }
+        if (!solve6(G, g, d)) { st->status = ST_STATIONARY; st->done = 1; return; }
+    } else {
+        for (int k = 0; k < 6; ++k) d[k] = g[k];
+    }
+    const double slope = g[0] * d[0] + g[1] * d[1] + g[2] * d[2] + g[3] * d[3] + g[4] * d[4] + g[5] * d[5];
+    const double curv_d = quad_form(tot, d);
+    const double tauN = (curv_d < 0.0) ? slope / (-curv_d) : INFINITY;
+    const double nw = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double nv = sqrt(d[3] * d[3] + d[4] * d[4] + d[5] * d[5]);
     const double tauC = ac->step_lambda * ell / (nw * tot[R_RMAX] + nv);
     const double tau = tauN < tauC ? tauN : tauC;
     double xi[6], E[12];
-    for (int k = 0; k < 6; ++k) xi[k] = tau * g[k];
+    for (int k = 0; k < 6; ++k) xi[k] = tau * d[k];
     exp_se3(xi, E);
     compose_left(E, st->T);
     invert_pose(st->T, st->Tinv);
@@ -139,7 +206,7 @@ __device__ void finalize_pair(PairState *st, const AlignConst *ac, const double 
         tr[4] = tau;
         tr[5] = ind;
         tr[6] = np;
-        tr[7] = curv;
+        tr[7] = curv_d;
     }
     st->it = it + 1;
     st->total_pairs += np;
@@ -166,6 +233,7 @@ __device__ void finalize_pair(PairState *st, const AlignConst *ac, const double 
 
 __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
 {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && a.ticket) *a.ticket = 0u;
     const int b = blockIdx.y;
     PairState *st = a.state + b;
     if (st->done) return;
@@ -187,12 +255,29 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
                              T[4] * zq.x + T[5] * zq.y + T[6] * zq.z + T[7],
                              T[8] * zq.x + T[9] * zq.y + T[10] * zq.z + T[11]};
         acc[R_RMAX] = fmax(acc[R_RMAX], sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]));
-        const int nj = a.cnt[j];
+        for (int k = 0; k < 3; ++k) acc[R_ZS + k] += z[k];
+        acc[R_ZZ + 0] += z[0] * z[0];
+        acc[R_ZZ + 1] += z[0] * z[1];
+        acc[R_ZZ + 2] += z[0] * z[2];
+        acc[R_ZZ + 3] += z[1] * z[1];
+        acc[R_ZZ + 4] += z[1] * z[2];
+        acc[R_ZZ + 5] += z[2] * z[2];
+        // combine this query's partial moments over its cluster's pieces
+        const int c = a.map.tclus[j];
+        const int t = (int)(j - a.map.clus[c].x);
+        const int2 cp = a.map.cpieces[c];
+        int nj = 0;
+        double Wt = 0.0, Dsum[3] = {0.0, 0.0, 0.0}, Ssum[6] = {0, 0, 0, 0, 0, 0};
+        for (int i = cp.x; i < cp.x + cp.y; ++i) {
+            const long long o = (long long)a.map.pieces[i].w + t;
+            nj += a.cnt[o];
+            Wt += a.W[o];
+            for (int k = 0; k < 3; ++k) Dsum[k] += a.D[3 * o + k];
+            for (int k = 0; k < 6; ++k) Ssum[k] += (double)a.S[6 * o + k];
+        }
         if (nj == 0) continue;
-        const double Wt = a.W[j];
-        const double Dt[3] = {a.D[3 * j] * isc, a.D[3 * j + 1] * isc, a.D[3 * j + 2] * isc};
-        const float *Sp = a.S + 6 * j;
-        const double S6[6] = {Sp[0] * ia, Sp[1] * ia, Sp[2] * ia, Sp[3] * ia, Sp[4] * ia, Sp[5] * ia};
+        const double Dt[3] = {Dsum[0] * isc, Dsum[1] * isc, Dsum[2] * isc};
+        const double S6[6] = {Ssum[0] * ia, Ssum[1] * ia, Ssum[2] * ia, Ssum[3] * ia, Ssum[4] * ia, Ssum[5] * ia};
         acc[R_F] += Wt;
         acc[R_OM + 0] += z[1] * Dt[2] - z[2] * Dt[1];
         acc[R_OM + 1] += z[2] * Dt[0] - z[0] * Dt[2];
@@ -223,7 +308,7 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
     }
 
     // block reduction: lanes (xor tree), then waves in order
-    for (int k = 0; k < R_RMAX + 1; ++k) {
+    for (int k = 0; k < R_END; ++k) {
         double v = acc[k];
         for (int off = kWave / 2; off > 0; off >>= 1) {
             const double o = __shfl_xor(v, off);
@@ -235,10 +320,10 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
     __shared__ int s_last;
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     if (lane == 0)
-        for (int k = 0; k < kRedVals; ++k) red[wv][k] = acc[k];
+        for (int k = 0; k < R_END; ++k) red[wv][k] = acc[k];
     __syncthreads();
     double *part = a.partials + ((long long)b * a.nblk + blockIdx.x) * kRedVals;
-    if (threadIdx.x < kRedVals) {
+    if (threadIdx.x < R_END) {
         double v = red[0][threadIdx.x];
         for (int w = 1; w < kRedThreads / kWave; ++w)
             v = (threadIdx.x == R_RMAX) ? fmax(v, red[w][threadIdx.x]) : v + red[w][threadIdx.x];
@@ -253,12 +338,17 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
     __syncthreads();
     if (!s_last) return;
     __threadfence();
+    // gather every block partial of this pair at once (one round of loads),
+    // then combine each value over the blocks in block order
     __shared__ double tot[kRedVals];
-    if (threadIdx.x < kRedVals) {
-        const double *pb = a.partials + (long long)b * a.nblk * kRedVals;
+    __shared__ double parts[64 * kRedVals];
+    const double *pb = a.partials + (long long)b * a.nblk * kRedVals;
+    for (int k = threadIdx.x; k < a.nblk * kRedVals; k += kRedThreads) parts[k] = pb[k];
+    __syncthreads();
+    if (threadIdx.x < R_END) {
         double v = 0.0;
         for (int k = 0; k < a.nblk; ++k) {
-            const double p = pb[(long long)k * kRedVals + threadIdx.x];
+            const double p = parts[k * kRedVals + threadIdx.x];
             v = (threadIdx.x == R_RMAX) ? fmax(v, p) : v + p;
         }
         tot[threadIdx.x] = v;
@@ -290,16 +380,28 @@ __global__ void backward_finish(const BackwardArgs a)
     for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < a.n;
          p += (long long)gridDim.x * blockDim.x) {
         const long long o = a.qperm[p];
+        const int c = a.map.tclus[p];
+        const int t = (int)(p - a.map.clus[c].x);
+        const int2 cp = a.map.cpieces[c];
         if (a.dxyz) {
-            const double d0 = a.D[3 * p], d1 = a.D[3 * p + 1], d2 = a.D[3 * p + 2];
+            double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+            for (int i = cp.x; i < cp.x + cp.y; ++i) {
+                const long long s = (long long)a.map.pieces[i].w + t;
+                d0 += a.D[3 * s];
+                d1 += a.D[3 * s + 1];
+                d2 += a.D[3 * s + 2];
+            }
             for (int k = 0; k < 3; ++k)
                 a.dxyz[3 * o + k] = (float)(f * (P[k] * d0 + P[4 + k] * d1 + P[8 + k] * d2));
         }
         if (a.dfeat) {
             for (int k = 0; k < a.lay.d4; ++k) {
                 const int col = a.lay.col[k];
-                if (col >= 0)
-                    a.dfeat[o * a.lay.src_dim + col] = (float)(a.gF * a.G[p * a.lay.d4 + k] * a.lay.gscale[k]);
+                if (col < 0) continue;
+                double gk = 0.0;
+                for (int i = cp.x; i < cp.x + cp.y; ++i)
+                    gk += a.G[((long long)a.map.pieces[i].w + t) * a.lay.d4 + k];
+                a.dfeat[o * a.lay.src_dim + col] = (float)(a.gF * gk * a.lay.gscale[k]);
             }
         }
     }

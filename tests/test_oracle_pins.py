@@ -485,3 +485,67 @@ def test_pair_count_matches_independent_count_with_adversarial_boundaries():
             s = (dx * dx + dy * dy) + dz * dz
             cnt += s <= rc2
     assert r["n_pairs"] == cnt
+
+
+# ------------------------------------------------------------ metric on se(3) for the ascent
+def test_metric_is_mean_squared_point_velocity():
+    """xi^T G xi equals the mean over the moving cloud of |omega x z' + v|^2
+    (plus the small rotation regulariser mu |omega|^2)."""
+    rng = np.random.default_rng(41)
+    z = rng.normal(size=(300, 3)) * np.array([3.0, 1.0, 10.0]) + np.array([0.5, -1.0, 8.0])
+    T = oracle.exp_se3([0.1, -0.2, 0.05, 0.3, 0.1, -0.4])
+    G = oracle.metric_tensor(T, z)
+    zt = oracle.transform(T, z)
+    mu = 1e-6 * (np.mean(np.sum(zt * zt, axis=1)) + 1e-12)
+    for _ in range(5):
+        xi = rng.normal(size=6)
+        vel = np.cross(xi[:3], zt) + xi[3:]
+        ke = np.mean(np.sum(vel * vel, axis=1)) + mu * xi[:3] @ xi[:3]
+        assert xi @ G @ xi == pytest.approx(ke, rel=1e-12)
+    np.testing.assert_allclose(G, G.T, atol=0)
+    assert np.all(np.linalg.eigvalsh(G) > 0)
+
+
+def test_metric_regularised_for_degenerate_clouds():
+    for z in (np.array([[1.0, 2.0, 3.0]]), np.array([[0.0, 0.0, t] for t in range(5)])):
+        G = oracle.metric_tensor(np.eye(4), z)
+        assert np.all(np.linalg.eigvalsh(G) > 0)
+
+
+def test_solve6_matches_library_solve():
+    rng = np.random.default_rng(42)
+    A = rng.normal(size=(6, 6))
+    G = A @ A.T + 0.1 * np.eye(6)
+    g = rng.normal(size=6)
+    np.testing.assert_allclose(oracle.solve6(G, g), np.linalg.solve(G, g), rtol=1e-10, atol=1e-12)
+
+
+def test_curvature_along_any_direction_matches_second_difference():
+    p = _small(seed=43)
+    T = oracle.exp_se3([0.02, -0.01, 0.03, 0.01, 0.01, 0.02])
+    d = np.array([0.3, -0.2, 0.5, 0.1, -0.4, 0.2])
+    r = oracle.evaluate(p.x, p.u, p.z, p.v, p.spec, 0.15, T=T, kappa=INF, direction=d)
+
+    def phi(t):
+        return oracle.evaluate(p.x, p.u, p.z, p.v, p.spec, 0.15, T=_twist_pose(t * d, T), kappa=INF)["F"]
+
+    h = 1e-3
+    d2a = (phi(h) - 2 * phi(0) + phi(-h)) / h ** 2
+    d2b = (phi(h / 2) - 2 * phi(0) + phi(-h / 2)) / (h / 2) ** 2
+    assert r["phi2"] == pytest.approx((4 * d2b - d2a) / 3, rel=1e-5, abs=1e-6 * r["absF"] / 0.15 ** 2)
+    # the slope along d is grad . d
+    fd1 = (phi(h / 2) - phi(-h / 2)) / h
+    assert r["grad"] @ d == pytest.approx(fd1, rel=1e-5, abs=1e-7 * np.max(r["absgrad"]))
+
+
+def test_identity_metric_ascent_also_recovers():
+    p = synth.tiny_cube()
+    prm = dict(p.align, metric=oracle.METRIC_IDENTITY)
+    T, rep, tr = oracle.align(p.x, p.u, p.z, p.v, p.spec, prm)
+    E = np.linalg.inv(p.T_gt) @ T
+    assert np.rad2deg(np.linalg.norm(Rotation.from_matrix(E[:3, :3]).as_rotvec())) < 0.2
+    # with the kinetic metric the same fixed run ends at the same optimum
+    T2, _, _ = oracle.align(p.x, p.u, p.z, p.v, p.spec, p.align)
+    E2 = np.linalg.inv(T) @ T2
+    assert np.linalg.norm(Rotation.from_matrix(E2[:3, :3]).as_rotvec()) < 1e-4
+    assert np.linalg.norm(E2[:3, 3]) < 1e-4
