@@ -75,7 +75,8 @@ class cvo_eval(C.Structure):
 
 class cvo_tuning(C.Structure):
     _fields_ = [("cluster_max", C.c_int32), ("cell_factor", C.c_double), ("cluster_factor", C.c_double),
-                ("rebuild_ratio", C.c_double), ("unroll", C.c_int32), ("piece_work", C.c_int32)]
+                ("rebuild_ratio", C.c_double), ("unroll", C.c_int32), ("piece_work", C.c_int32),
+                ("adaptive", C.c_int32)]
 
 
 class cvo_timing(C.Structure):

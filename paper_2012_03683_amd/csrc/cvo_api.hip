@@ -15,7 +15,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/cvo.h"
+#include "cvo.h"
 #include "cvo_launch.hpp"
 
 namespace cvo {
@@ -58,10 +58,9 @@ struct cvo_context {
         size_t cap = 0;
     };
     std::map<std::string, Buf> bufs;
-    unsigned long long generation = 0;  // bumps whenever a buffer moves
     void *pinned = nullptr;
     size_t pinned_cap = 0;
-    cvo_tuning tuning{16, 1.0, 0.5, 0.5, 8, 16384};
+    cvo_tuning tuning{16, 1.0, 0.5, 0.6, 16, 16384, 1};
     bool profiling = false;
     cvo_timing timing{0, 0.0, 0, 0};
     std::vector<hipEvent_t> ev_free;
@@ -90,7 +89,6 @@ struct cvo_context {
                                                           " bytes for " + name + " failed");
             }
             b.cap = cap;
-            ++generation;
         }
         return b.p;
     }
@@ -349,8 +347,30 @@ std::vector<float> cloud_boxes(cvo_context *ctx, const std::string &pre, const s
     return box;
 }
 
+// Shape of the views of one pair: query points per cluster and grid cell edge
+// relative to the cutoff radius.
+struct ViewShape {
+    int cluster_max;
+    double cell_factor;
+    bool operator==(const ViewShape &o) const { return cluster_max == o.cluster_max && cell_factor == o.cell_factor; }
+};
+
+ViewShape fixed_shape(const cvo_context *ctx) { return ViewShape{ctx->tuning.cluster_max, ctx->tuning.cell_factor}; }
+
+// Shape for a density class (density_class of the in-cutoff pairs per query
+// point; -1 when unknown).  Dense bands amortise each candidate load over
+// more queries and cut the neighbourhood finer; sparse bands keep clusters
+// small.
+ViewShape density_shape(const cvo_context *ctx, int cls)
+{
+    if (!ctx->tuning.adaptive) return fixed_shape(ctx);
+    if (cls == 2) return ViewShape{64, 0.5};
+    if (cls == 1) return ViewShape{32, 0.5};
+    return fixed_shape(ctx);
+}
+
 GridView build_grid(cvo_context *ctx, const std::string &pre, const std::vector<CloudPtrs> &cl,
-                    const std::vector<double> &rc, const FeatLayout &lay)
+                    const std::vector<double> &rc, const FeatLayout &lay, const std::vector<ViewShape> &shape)
 {
     GridView v;
     const int B = (int)cl.size();
@@ -358,7 +378,6 @@ GridView build_grid(cvo_context *ctx, const std::string &pre, const std::vector<
     v.rc = rc;
     CloudPtrs *dc = nullptr;
     std::vector<float> box = cloud_boxes(ctx, pre, cl, &dc);
-    const double cell_factor = ctx->tuning.cell_factor;
     const long long cell_cap = 1LL << 23;
     v.desc.resize(B);
     long long cell_base = 0, pt_base = 0, max_cells = 0, nmax = 0;
@@ -370,18 +389,22 @@ GridView build_grid(cvo_context *ctx, const std::string &pre, const std::vector<
         if (n == 0) {
             g.ox = g.oy = g.oz = 0.0;
             g.h = 1.0;
+            g.inv_h = 1.0;
             g.nx = g.ny = g.nz = 1;
         } else {
             const double lo[3] = {box[8 * c], box[8 * c + 1], box[8 * c + 2]};
             const double hi[3] = {box[8 * c + 3], box[8 * c + 4], box[8 * c + 5]};
             double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-6});
-            double h = std::isfinite(rc[c]) ? cell_factor * rc[c] : ext * 1.01;
+            double h = std::isfinite(rc[c]) ? shape[c].cell_factor * rc[c] : ext * 1.01;
             h = std::max(h, ext * 1e-6);
             int nn[3];
+            double inv = 1.0 / h;
             for (;;) {
+                inv = 1.0 / h;
                 long long tot = 1;
                 for (int k = 0; k < 3; ++k) {
-                    nn[k] = (int)std::floor((hi[k] - lo[k]) / h) + 1;
+                    // same expression as the device binning: floor((p - o) * inv_h)
+                    nn[k] = (int)std::floor((hi[k] - lo[k]) * inv) + 1;
                     tot *= nn[k];
                 }
                 if (tot <= cell_cap && nn[0] < (1 << 30) / std::max(1, nn[1])) break;
@@ -391,6 +414,7 @@ GridView build_grid(cvo_context *ctx, const std::string &pre, const std::vector<
             g.oy = lo[1];
             g.oz = lo[2];
             g.h = h;
+            g.inv_h = inv;
             g.nx = nn[0];
             g.ny = nn[1];
             g.nz = nn[2];
@@ -440,7 +464,7 @@ GridView build_grid(cvo_context *ctx, const std::string &pre, const std::vector<
 }
 
 ClusterView build_clusters(cvo_context *ctx, const std::string &pre, const std::vector<CloudPtrs> &cl,
-                           const std::vector<double> &rc, const FeatLayout &lay)
+                           const std::vector<double> &rc, const FeatLayout &lay, const std::vector<ViewShape> &shape)
 {
     ClusterView v;
     const int B = (int)cl.size();
@@ -450,9 +474,8 @@ ClusterView build_clusters(cvo_context *ctx, const std::string &pre, const std::
     std::vector<float> box = cloud_boxes(ctx, pre, cl, &dc);
     const int cbits = bits_for((unsigned long long)(B > 1 ? B - 1 : 0));
     const int maxbits = std::min(19, (62 - cbits) / 3);
-    const int tpw = ctx->tuning.cluster_max;
     std::vector<ClusterBuild> cb(B);
-    std::vector<int> lcap(B);
+    std::vector<int2> lcap(B);  // (largest octree level, max points per cluster)
     std::vector<long long> bases(B);
     v.desc.resize(B);
     long long pt_base = 0, nmax = 0;
@@ -480,7 +503,7 @@ ClusterView build_clusters(cvo_context *ctx, const std::string &pre, const std::
         g.q = q;
         g.pt_base = pt_base;
         g.n = n;
-        lcap[c] = L;
+        lcap[c] = make_int2(L, shape[c].cluster_max);
         bases[c] = pt_base;
         ClusterDesc &d = v.desc[c];
         d.clus_base = 0;
@@ -496,8 +519,8 @@ ClusterView build_clusters(cvo_context *ctx, const std::string &pre, const std::
     ctx->upload(d_cb, cb.data(), sizeof(ClusterBuild) * B);
     long long *d_base = ctx->get_t<long long>(pre + ".base", B);
     ctx->upload(d_base, bases.data(), sizeof(long long) * B);
-    int *d_lcap = ctx->get_t<int>(pre + ".lcap", B);
-    ctx->upload(d_lcap, lcap.data(), sizeof(int) * B);
+    int2 *d_lcap = ctx->get_t<int2>(pre + ".lcap", B);
+    ctx->upload(d_lcap, lcap.data(), sizeof(int2) * B);
     v.d_desc = ctx->get_t<ClusterDesc>(pre + ".desc", B);
 
     const long long ntot = std::max(v.ntot, 1LL);
@@ -526,7 +549,7 @@ ClusterView build_clusters(cvo_context *ctx, const std::string &pre, const std::
         launch_radix_sort(keys, vals, ktmp, vtmp, hist, bsum, v.ntot, 3 * bits + cbits, ctx->stream, &in_tmp);
         if (in_tmp) { std::swap(keys, ktmp); std::swap(vals, vtmp); }
         launch_gather(keys, vals, v.ntot, 3 * bits, dc, d_base, lay, v.pts, v.feat, v.perm, ctx->stream);
-        launch_cluster_heads(keys, v.ntot, d_lcap, 3 * bits, tpw, head, span, ctx->stream);
+        launch_cluster_heads(keys, v.ntot, d_lcap, 3 * bits, head, span, ctx->stream);
         launch_exclusive_scan(head, hidx, bsum, v.ntot, d_total, ctx->stream);
         launch_cluster_emit(head, hidx, span, v.pts, keys, 3 * bits, v.ntot, v.clus, v.cgeo, v.cpair, v.tclus,
                             ctx->stream);
@@ -544,19 +567,18 @@ ClusterView build_clusters(cvo_context *ctx, const std::string &pre, const std::
 // `piece_work` query x candidate products (planned at the pose in the device
 // state), and the pieces are processed heaviest first.
 struct Plan {
+    int4 *qmap = nullptr;   // per query: (t, first piece, pieces, first slot)
     int4 *pieces = nullptr;
     int *porder = nullptr;
     int2 *cpieces = nullptr;
     int npieces = 0;
     long long nslots = 0;
-    unsigned int *ticket = nullptr;
 };
 
 Plan make_plan(cvo_context *ctx, const std::string &pre, const ClusterView &q, const GridView &r,
                const PairState *d_state, int inverse, double kappa)
 {
     Plan pl;
-    pl.ticket = ctx->get_t<unsigned int>(pre + ".ticket", 1);
     if (q.nclus == 0) return pl;
     PairPassArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -596,14 +618,15 @@ Plan make_plan(cvo_context *ctx, const std::string &pre, const ClusterView &q, c
     launch_plan_emit(a, npc, pbase, cmax, ccount, pl.pieces, pn, key, val, pl.cpieces, ctx->stream);
     launch_exclusive_scan(pn, tbase, bsum2, P, d_total + 1, ctx->stream);
     launch_plan_slots(pl.pieces, tbase, P, ctx->stream);
+    pl.qmap = ctx->get_t<int4>(pre + ".qmap", std::max<long long>(q.ntot, 1));
+    launch_plan_qmap(q.clus, pl.cpieces, pl.pieces, nc, pl.qmap, ctx->stream);
     bool in_tmp = false;
     launch_radix_sort(key, val, ktmp, vtmp, hist, bsum2, P, 32, ctx->stream, &in_tmp);
     pl.porder = in_tmp ? vtmp : val;
     ctx->check_launch("plan emit");
-    int S = 0;
-    ctx->download(&S, d_total + 1, sizeof(int));
-    pl.nslots = S;
-    HIP_OK(hipMemsetAsync(pl.ticket, 0, sizeof(unsigned int), ctx->stream));
+    int nslots = 0;
+    ctx->download(&nslots, d_total + 1, sizeof(int));
+    pl.nslots = nslots;
     return pl;
 }
 
@@ -660,17 +683,15 @@ PairPassArgs pass_args(const ClusterView &q, const GridView &r, const PairState 
     a.pieces = pl.pieces;
     a.porder = pl.porder;
     a.npieces = pl.npieces;
-    a.ticket = pl.ticket;
     return a;
 }
 
 SlotMap slot_map(const ClusterView &q, const Plan &pl)
 {
     SlotMap m;
-    m.tclus = q.tclus;
-    m.clus = q.clus;
-    m.cpieces = pl.cpieces;
+    m.qmap = pl.qmap;
     m.pieces = pl.pieces;
+    (void)q;
     return m;
 }
 
@@ -696,8 +717,8 @@ int reduce_blocks(const std::vector<ClusterDesc> &cd)
 {
     long long mx = 1;
     for (auto &d : cd) mx = std::max(mx, (long long)d.n);
-    long long nb = (mx + 4 * kRedThreads - 1) / (4 * kRedThreads);
-    return (int)std::min(std::max(nb, 1LL), 64LL);
+    long long nb = (mx + kRedThreads - 1) / kRedThreads;
+    return (int)std::min(std::max(nb, 1LL), 512LL);
 }
 
 PairState init_state(const double *T, double ell)
@@ -713,6 +734,8 @@ PairState init_state(const double *T, double ell)
     s.i_prev = NAN;
     s.status = ST_RUNNING;
     s.done = 0;
+    s.cls_built = -1;
+    s.pause = 0;
     return s;
 }
 
@@ -723,6 +746,7 @@ struct Problem {
     ClusterView clus;    // Z clouds, query role
     Plan plan;
     Moments mom;
+    std::vector<ViewShape> shape;  // per pair, of the current views
     PairState *d_state = nullptr;
     AlignConst *d_ac = nullptr;
     double *partials = nullptr;
@@ -735,12 +759,13 @@ struct Problem {
 // Grid of X, clusters of Z, and the work plan at the pose held in the device
 // state (which must be current).
 void build_views(cvo_context *ctx, Problem &p, const std::vector<CloudPtrs> &X, const std::vector<CloudPtrs> &Z,
-                 const std::vector<double> &ell)
+                 const std::vector<double> &ell, const std::vector<ViewShape> &shape)
 {
+    p.shape = shape;
     std::vector<double> rc(ell.size());
     for (size_t k = 0; k < ell.size(); ++k) rc[k] = p.kappa * ell[k];
-    p.grid = build_grid(ctx, "fx", X, rc, p.lay);
-    p.clus = build_clusters(ctx, "fz", Z, rc, p.lay);
+    p.grid = build_grid(ctx, "fx", X, rc, p.lay, shape);
+    p.clus = build_clusters(ctx, "fz", Z, rc, p.lay, shape);
     p.plan = make_plan(ctx, "fp", p.clus, p.grid, p.d_state, 0, p.kappa);
     p.mom = moments(ctx, "fm", p.plan.nslots, p.lay.d4, false);
 }
@@ -753,7 +778,7 @@ void setup_problem(cvo_context *ctx, Problem &p, const std::vector<CloudPtrs> &X
     for (int b = 0; b < B; ++b) ell[b] = st[b].ell;
     p.d_state = ctx->get_t<PairState>("state", B);
     ctx->upload(p.d_state, st.data(), sizeof(PairState) * B);
-    build_views(ctx, p, X, Z, ell);
+    build_views(ctx, p, X, Z, ell, std::vector<ViewShape>(B, fixed_shape(ctx)));
     p.d_ac = ctx->get_t<AlignConst>("aconst", B);
     ctx->upload(p.d_ac, ac.data(), sizeof(AlignConst) * B);
     p.nblk = reduce_blocks(p.clus.desc);
@@ -762,21 +787,15 @@ void setup_problem(cvo_context *ctx, Problem &p, const std::vector<CloudPtrs> &X
     HIP_OK(hipMemsetAsync(p.counters, 0, sizeof(unsigned int) * B, ctx->stream));
 }
 
-void enqueue_iteration(cvo_context *ctx, Problem &p, int mode, double *trace, long long trace_rows, bool timed)
+// Kernel arguments of one ascent iteration (pair pass, then reduction).
+void iteration_args(const Problem &p, int mode, double *trace, long long trace_rows, PairPassArgs &a,
+                    ReduceArgs &r)
 {
-    PairPassArgs a = pass_args(p.clus, p.grid, p.d_state, 0, p.sig2, p.kappa, p.mom, p.plan);
-    if (timed) run_pair_pass(ctx, a, p.lay, 0);
-    else {
-        if (!launch_pair_pass(a, p.lay, 0, ctx->stream))
-            throw CvoError(CVO_ERR_UNSUPPORTED, "no compiled pair kernel for the feature layout");
-        ctx->timing.evaluations += 1;
-    }
-    ReduceArgs r;
+    a = pass_args(p.clus, p.grid, p.d_state, 0, p.sig2, p.kappa, p.mom, p.plan);
     std::memset(&r, 0, sizeof(r));
     r.qpts = p.clus.pts;
     r.cdesc = p.clus.d_desc;
     r.map = slot_map(p.clus, p.plan);
-    r.ticket = p.plan.ticket;
     r.W = p.mom.W;
     r.D = p.mom.D;
     r.S = p.mom.S;
@@ -789,8 +808,38 @@ void enqueue_iteration(cvo_context *ctx, Problem &p, int mode, double *trace, lo
     r.trace_rows = trace_rows;
     r.nblk = p.nblk;
     r.mode = mode;
+}
+
+void enqueue_iteration(cvo_context *ctx, Problem &p, int mode, double *trace, long long trace_rows, bool timed)
+{
+    PairPassArgs a;
+    ReduceArgs r;
+    iteration_args(p, mode, trace, trace_rows, a, r);
+    if (timed) run_pair_pass(ctx, a, p.lay, 0);
+    else {
+        if (!launch_pair_pass(a, p.lay, 0, ctx->stream))
+            throw CvoError(CVO_ERR_UNSUPPORTED, "no compiled pair kernel for the feature layout");
+        ctx->timing.evaluations += 1;
+    }
     launch_reduce(r, p.grid.B, ctx->stream);
     ctx->check_launch("reduce");
+}
+
+// Everything a captured run of U iterations bakes into its launches: the
+// kernel arguments (buffers, counts, plan), the feature layout, the batch
+// size and U.  A graph is replayed only while this key is unchanged.
+std::string iteration_key(const Problem &p, double *trace, long long trace_rows, int B, int U)
+{
+    PairPassArgs a;
+    ReduceArgs r;
+    iteration_args(p, 1, trace, trace_rows, a, r);
+    std::string k;
+    k.append(reinterpret_cast<const char *>(&a), sizeof(a));
+    k.append(reinterpret_cast<const char *>(&r), sizeof(r));
+    k.append(reinterpret_cast<const char *>(&p.lay), sizeof(p.lay));
+    k.append(reinterpret_cast<const char *>(&B), sizeof(B));
+    k.append(reinterpret_cast<const char *>(&U), sizeof(U));
+    return k;
 }
 
 CloudPtrs to_ptrs(const cvo_cloud *c)
@@ -816,10 +865,14 @@ AlignConst const_for(const cvo_align_params *ap, long long N, long long M)
         a.max_iter = ap->max_iter;
         a.fixed_iters = ap->fixed_iters;
         a.metric = ap->metric;
+        a.kappa = ap->kappa;
     } else {
         a.max_iter = 1;
         a.step_lambda = 1.0;
+        a.kappa = INFINITY;
     }
+    a.rebuild_ratio = 1.0;
+    a.adaptive = 0;
     a.sqrt_nm = std::sqrt((double)N * (double)M);
     a.inv_m = M > 0 ? 1.0 / (double)M : 0.0;
     return a;
@@ -903,12 +956,17 @@ void align_many(cvo_context *ctx, const std::vector<CloudPtrs> &X, const std::ve
     p.kappa = prm[0].kappa;
     p.lay = make_layout(spec, prm[0].sigma);
     p.sig2 = p.lay.sig2;
+    const bool cut = std::isfinite(p.kappa);
+    const bool adapt = cut && ctx->tuning.adaptive;
     std::vector<PairState> st(B);
     std::vector<AlignConst> ac(B);
     long long trace_rows = 0;
     for (int b = 0; b < B; ++b) {
         st[b] = init_state(T0[b], prm[b].ell_init);
+        st[b].rc_build = p.kappa * prm[b].ell_init;
         ac[b] = const_for(&prm[b], X[b].n, Z[b].n);
+        ac[b].rebuild_ratio = ctx->tuning.rebuild_ratio;
+        ac[b].adaptive = adapt ? 1 : 0;
         if (X[b].n == 0 || Z[b].n == 0) {
             st[b].status = ST_NO_OVERLAP;
             st[b].done = 1;
@@ -918,14 +976,19 @@ void align_many(cvo_context *ctx, const std::vector<CloudPtrs> &X, const std::ve
     double *d_trace = trace_host ? ctx->get_t<double>("trace", (size_t)B * trace_rows * kTraceLen) : nullptr;
     setup_problem(ctx, p, X, Z, st, ac);
     const int U = std::max(1, std::min(64, (int)ctx->tuning.unroll));
-    const bool cut = std::isfinite(p.kappa);
+    // Views are rebuilt only where the device paused a pair (its cutoff
+    // shrank, or its pair density fell a class) -- a function of the iterates
+    // alone.  With adaptive shapes, the first iteration runs by itself and its
+    // measured density picks the first shape.
+    std::vector<double> ell_build(B);
+    for (int b = 0; b < B; ++b) ell_build[b] = prm[b].ell_init;
+    bool probe = adapt;
     std::vector<PairState> now(B);
-    PairState *h_state = static_cast<PairState *>(ctx->host(sizeof(PairState) * B));
-    (void)h_state;
     for (;;) {
-        if (use_graph) {
-            const std::string key = std::to_string(ctx->generation) + ":" + std::to_string(p.clus.nclus) + ":" +
-                                    std::to_string(B) + ":" + std::to_string(U);
+        if (probe) {
+            enqueue_iteration(ctx, p, 1, d_trace, trace_rows, ctx->profiling);
+        } else if (use_graph) {
+            const std::string key = iteration_key(p, d_trace, trace_rows, B, U);
             if (!ctx->graph || ctx->graph_key != key) {
                 if (ctx->graph) HIP_OK(hipGraphExecDestroy(ctx->graph));
                 ctx->graph = nullptr;
@@ -950,19 +1013,28 @@ void align_many(cvo_context *ctx, const std::vector<CloudPtrs> &X, const std::ve
         }
         ctx->download(now.data(), p.d_state, sizeof(PairState) * B);
         if (ctx->profiling) ctx->harvest_events();
-        bool all_done = true, rebuild = false;
+        bool all_done = true, rebuild = false, changed = false;
+        std::vector<ViewShape> shape = p.shape;
         for (int b = 0; b < B; ++b) {
-            if (!now[b].done) {
-                all_done = false;
-                if (cut && p.kappa * now[b].ell < ctx->tuning.rebuild_ratio * p.grid.rc[b]) rebuild = true;
+            if (now[b].done) continue;
+            all_done = false;
+            if (!probe && !now[b].pause) continue;
+            const int cls = adapt ? density_class(now[b].n_pairs / (double)std::max(Z[b].n, 1LL)) : -1;
+            const ViewShape want = adapt ? density_shape(ctx, cls) : fixed_shape(ctx);
+            if (now[b].pause || !(want == p.shape[b])) {
+                rebuild = true;
+                ell_build[b] = now[b].ell;
+                shape[b] = want;
+                now[b].rc_build = p.kappa * now[b].ell;
             }
+            now[b].cls_built = cls;
+            now[b].pause = 0;
+            changed = true;
         }
+        probe = false;
         if (all_done) break;
-        if (rebuild) {
-            std::vector<double> ell(B);
-            for (int b = 0; b < B; ++b) ell[b] = now[b].ell;
-            build_views(ctx, p, X, Z, ell);
-        }
+        if (rebuild) build_views(ctx, p, X, Z, ell_build, shape);
+        if (changed) ctx->upload(p.d_state, now.data(), sizeof(PairState) * B);
     }
     final_state = now;
     if (ctx->profiling)
@@ -1180,8 +1252,8 @@ cvo_status cvo_inner_product_backward(cvo_handle h, const cvo_cloud *X, const cv
         h->upload(d_state, &s0, sizeof(PairState));
         // target side: queries Z (pose T) against the X grid
         if (dZ || dV || dEll) {
-            GridView gx = build_grid(h, "fx", {to_ptrs(X)}, {rc}, lay);
-            ClusterView cz = build_clusters(h, "fz", {to_ptrs(Z)}, {rc}, lay);
+            GridView gx = build_grid(h, "fx", {to_ptrs(X)}, {rc}, lay, {fixed_shape(h)});
+            ClusterView cz = build_clusters(h, "fz", {to_ptrs(Z)}, {rc}, lay, {fixed_shape(h)});
             Plan pl = make_plan(h, "bp", cz, gx, d_state, 0, kp->kappa);
             Moments m = moments(h, "bm", pl.nslots, lay.d4, true);
             PairPassArgs a = pass_args(cz, gx, d_state, 0, lay.sig2, kp->kappa, m, pl);
@@ -1212,8 +1284,8 @@ cvo_status cvo_inner_product_backward(cvo_handle h, const cvo_cloud *X, const cv
         }
         // source side: queries X (pose T^-1) against the Z grid
         if (dX || dU) {
-            GridView gz = build_grid(h, "rz", {to_ptrs(Z)}, {rc}, lay);
-            ClusterView cx = build_clusters(h, "rx", {to_ptrs(X)}, {rc}, lay);
+            GridView gz = build_grid(h, "rz", {to_ptrs(Z)}, {rc}, lay, {fixed_shape(h)});
+            ClusterView cx = build_clusters(h, "rx", {to_ptrs(X)}, {rc}, lay, {fixed_shape(h)});
             Plan pl = make_plan(h, "bq", cx, gz, d_state, 1, kp->kappa);
             Moments m = moments(h, "bm2", pl.nslots, lay.d4, true);
             PairPassArgs a = pass_args(cx, gz, d_state, 1, lay.sig2, kp->kappa, m, pl);
@@ -1257,6 +1329,7 @@ cvo_status cvo_set_tuning(cvo_handle h, const cvo_tuning *in)
         require(in->rebuild_ratio > 0.0 && in->rebuild_ratio <= 1.0, "rebuild_ratio out of (0, 1]");
         require(in->unroll >= 1 && in->unroll <= 64, "unroll out of [1, 64]");
         require(in->piece_work >= 256 && in->piece_work <= (1 << 24), "piece_work out of [256, 2^24]");
+        require(in->adaptive == 0 || in->adaptive == 1, "adaptive must be 0 or 1");
         h->tuning = *in;
     });
 }
@@ -1317,7 +1390,6 @@ cvo_status cvo_autotune(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z, co
                 hipEvent_t e0 = h->event(), e1 = h->event();
                 std::vector<float> ms;
                 for (int rep = 0; rep < 4; ++rep) {
-                    HIP_OK(hipMemsetAsync(p.plan.ticket, 0, sizeof(unsigned int), h->stream));
                     HIP_OK(hipEventRecord(e0, h->stream));
                     if (!launch_pair_pass(a, p.lay, 0, h->stream))
                         throw CvoError(CVO_ERR_UNSUPPORTED, "no compiled pair kernel for the feature layout");
@@ -1338,6 +1410,7 @@ cvo_status cvo_autotune(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z, co
             }
         h->profiling = prof;
         h->timing = saved;
+        best.adaptive = 0;  // keep the measured winner in every band
         h->tuning = best;
         h->tune_cache[key] = best;
         if (chosen) *chosen = best;

@@ -56,13 +56,13 @@ __global__ __launch_bounds__(1024) void bbox_kernel(const CloudPtrs *clouds, flo
 }
 
 // ---------------------------------------------------------------- keys
-// Cell index along one axis: floor((p - o) / h) in FP64, clamped.  Division
-// (not multiplication by 1/h) keeps the host-side range computation and this
-// binning monotone in p, so a point inside [lo, hi] lands in a cell between
-// those of lo and hi.
-__device__ inline int cell_of(float p, double o, double h, int n)
+// Cell index along one axis: floor((p - o) * s) in FP64, clamped, with s the
+// same 1/h (or 1/q) the range computations use.  Subtraction and
+// multiplication by a positive constant are monotone under rounding, so a
+// point inside [lo, hi] lands in a cell between those of lo and hi.
+__device__ inline int cell_of(float p, double o, double s, int n)
 {
-    double f = floor(((double)p - o) / h);
+    double f = floor(((double)p - o) * s);
     f = fmin(fmax(f, 0.0), (double)(n - 1));
     return (int)f;
 }
@@ -76,9 +76,9 @@ __global__ void grid_keys(const CloudPtrs *clouds, const GridBuild *gb, unsigned
     const float *xyz = clouds[c].xyz;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
-        int ix = cell_of(xyz[3 * i + 0], g.ox, g.h, g.nx);
-        int iy = cell_of(xyz[3 * i + 1], g.oy, g.h, g.ny);
-        int iz = cell_of(xyz[3 * i + 2], g.oz, g.h, g.nz);
+        int ix = cell_of(xyz[3 * i + 0], g.ox, g.inv_h, g.nx);
+        int iy = cell_of(xyz[3 * i + 1], g.oy, g.inv_h, g.ny);
+        int iz = cell_of(xyz[3 * i + 2], g.oz, g.inv_h, g.nz);
         unsigned long long cell = (unsigned long long)ix +
                                   (unsigned long long)g.nx * ((unsigned long long)iy + (unsigned long long)g.ny * iz);
         keys[g.pt_base + i] = ((unsigned long long)c << kbits) | cell;
@@ -106,11 +106,12 @@ __global__ void morton_keys(const CloudPtrs *clouds, const ClusterBuild *cb, uns
     const long long n = clouds[c].n;
     const float *xyz = clouds[c].xyz;
     const int lim = (1 << bits);
+    const double iq = 1.0 / g.q;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
-        unsigned long long qx = (unsigned long long)cell_of(xyz[3 * i + 0], g.ox, g.q, lim);
-        unsigned long long qy = (unsigned long long)cell_of(xyz[3 * i + 1], g.oy, g.q, lim);
-        unsigned long long qz = (unsigned long long)cell_of(xyz[3 * i + 2], g.oz, g.q, lim);
+        unsigned long long qx = (unsigned long long)cell_of(xyz[3 * i + 0], g.ox, iq, lim);
+        unsigned long long qy = (unsigned long long)cell_of(xyz[3 * i + 1], g.oy, iq, lim);
+        unsigned long long qz = (unsigned long long)cell_of(xyz[3 * i + 2], g.oz, iq, lim);
         unsigned long long m = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
         keys[g.pt_base + i] = ((unsigned long long)c << (3 * bits)) | m;
         vals[g.pt_base + i] = (int)(g.pt_base + i);
@@ -342,16 +343,18 @@ __global__ void cell_table(const unsigned long long *keys, long long ntot, const
 
 // ---------------------------------------------------------------- clusters
 // A point's cluster is the largest aligned Morton block (level L <= lcap,
-// edge 2^L quanta) holding at most tpw points.  Block counts grow with L, so
-// every point of such a block makes the same choice.  A level-0 block with
-// more than tpw points is cut into ceil(count/tpw) near-equal chunks.
-__global__ void cluster_heads(const unsigned long long *keys, long long ntot, const int *lcaps, int cshift,
-                              int tpw, int *head, int2 *span)
+// edge 2^L quanta) holding at most tpw points, with (lcap, tpw) given per
+// cloud.  Block counts grow with L, so every point of such a block makes the
+// same choice.  A level-0 block with more than tpw points is cut into
+// ceil(count/tpw) near-equal chunks.
+__global__ void cluster_heads(const unsigned long long *keys, long long ntot, const int2 *caps, int cshift,
+                              int *head, int2 *span)
 {
     for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < ntot;
          p += (long long)gridDim.x * blockDim.x) {
         const unsigned long long key = keys[p];
-        const int lcap = lcaps[key >> cshift];
+        const int2 cap = caps[key >> cshift];
+        const int lcap = cap.x, tpw = cap.y;
         long long start = -1, end = -1;
         long long lo0 = 0, hi0 = 0;
         for (int L = lcap; L >= 0; --L) {
@@ -449,11 +452,11 @@ void launch_cell_table(const unsigned long long *keys, long long ntot, const Gri
                        gb, kbits, cell_start);
 }
 
-void launch_cluster_heads(const unsigned long long *keys, long long ntot, const int *lcaps, int cshift, int tpw,
+void launch_cluster_heads(const unsigned long long *keys, long long ntot, const int2 *caps, int cshift,
                           int *head, int2 *span, hipStream_t s)
 {
-    hipLaunchKernelGGL(cluster_heads, dim3(blocks_for(ntot, 256)), dim3(256), 0, s, keys, ntot, lcaps, cshift, tpw,
-                       head, span);
+    hipLaunchKernelGGL(cluster_heads, dim3(blocks_for(ntot, 256)), dim3(256), 0, s, keys, ntot, caps, cshift, head,
+                       span);
 }
 
 void launch_cluster_emit(const int *head, const int *hidx, const int2 *span, const float4 *pts,

@@ -43,25 +43,39 @@ struct alignas(16) PairState {
     double grad[6];
     double n_pairs;      // |P| of the last evaluation (exact integer in a double)
     double total_pairs;  // sum of |P| over the registration
+    double rc_build;     // cutoff radius the current views were built for
     long long it;        // steps taken
     int status;          // Status
     int done;            // nonzero: later launches skip this pair
+    int cls_built;       // pair-density class of the current views (-1: not chosen by density)
+    int pause;           // nonzero: views must be rebuilt; launches skip the pair until then
 };
+
+// Density class of an evaluation from its in-cutoff pairs per query point
+// (-1: unknown).  Dense classes get larger clusters and finer cells.
+__host__ __device__ inline int density_class(double ppq)
+{
+    return !(ppq >= 0.0) ? -1 : (ppq >= 2000.0 ? 2 : (ppq >= 500.0 ? 1 : 0));
+}
 
 // Per-pair constants of the ascent.
 struct alignas(16) AlignConst {
     double ell_min, decay, ind_rel_tol, eps_rot, eps_trans, step_lambda;
     double sqrt_nm;      // sqrt(|X| |Z|)
     double inv_m;        // 1 / |Z|
+    double kappa;        // cutoff radius / ell (infinite: no cutoff, views never rebuilt)
+    double rebuild_ratio; // pause for new views once kappa ell < rebuild_ratio * rc_build
     long long max_iter;
     int fixed_iters;
     int metric;          // 0: kinetic-energy metric of the moving cloud, 1: identity
+    int adaptive;        // nonzero: also pause when the density class drops below cls_built
 };
 
 // Uniform grid of one cloud (reference role).
 struct alignas(16) GridDesc {
     double ox, oy, oz;   // origin (cell (0,0,0) starts here)
     double h;            // cell edge (m)
+    double inv_h;        // 1 / h; a coordinate p lies in cell floor((p - o) * inv_h)
     int nx, ny, nz;
     int cell_base;       // offset of this cloud's table in cell_start
     long long pt_base;   // sorted points of this cloud: [pt_base, pt_base + n)
@@ -88,8 +102,8 @@ struct FeatLayout {
 
 // Arguments of the pair pass.  The unit of work is a piece: a contiguous
 // range [c0, c1) of one cluster's candidate list (the concatenation of its
-// neighbourhood rows), planned so that heavy clusters are split.  Persistent
-// waves take pieces heavy-first from an atomic ticket.
+// neighbourhood rows), planned so that heavy clusters are split.  One wave
+// per piece, pieces ordered heaviest first.
 struct PairPassArgs {
     // query side (cluster view)
     const float4 *qpts;
@@ -99,9 +113,8 @@ struct PairPassArgs {
     const int *cpair;     // pair of each cluster
     int nclus;
     const int4 *pieces;   // (cluster, c0, c1, first output slot), cluster-major
-    const int *porder;    // processing order of the pieces (heaviest first)
+    const int *porder;    // processing order of the pieces: heaviest first
     int npieces;
-    unsigned int *ticket; // zero before the launch
     // reference side (grid view)
     const float4 *rpts;
     const float *rfeat;

@@ -32,7 +32,7 @@ void launch_gather(const unsigned long long *keys, const int *vals, long long nt
                    float *feat, int *perm, hipStream_t s);
 void launch_cell_table(const unsigned long long *keys, long long ntot, const GridBuild *gb, int B,
                        long long max_cells, int kbits, int *cell_start, hipStream_t s);
-void launch_cluster_heads(const unsigned long long *keys, long long ntot, const int *lcaps, int cshift, int tpw,
+void launch_cluster_heads(const unsigned long long *keys, long long ntot, const int2 *caps, int cshift,
                           int *head, int2 *span, hipStream_t s);
 void launch_cluster_emit(const int *head, const int *hidx, const int2 *span, const float4 *pts,
                          const unsigned long long *keys, int cshift, long long ntot, int2 *clus, double4 *cgeo,
@@ -46,15 +46,15 @@ void launch_plan_emit(const PairPassArgs &a, const int *npieces, const int *pbas
                       const long long *ccount, int4 *pieces, int *pn, unsigned long long *key, int *val,
                       int2 *cpieces, hipStream_t s);
 void launch_plan_slots(int4 *pieces, const int *tbase, int npieces, hipStream_t s);
+void launch_plan_qmap(const int2 *clus, const int2 *cpieces, const int4 *pieces, int nclus, int4 *qmap,
+                      hipStream_t s);
 
-// Where a query's partial moments live: query j belongs to cluster tclus[j]
-// at position t = j - clus[c].x; that cluster's pieces are
-// [cpieces[c].x, cpieces[c].x + cpieces[c].y) and piece i keeps the query's
-// partial at slot pieces[i].w + t.  Partials are combined in piece order.
+// Where a query's partial moments live: qmap[j] = (t, first piece, number of
+// pieces, slot in the first piece) for query j at position t of its cluster;
+// piece i keeps the partial at slot pieces[i].w + t.  Partials are combined
+// in piece order.
 struct SlotMap {
-    const int *tclus;
-    const int2 *clus;
-    const int2 *cpieces;
+    const int4 *qmap;
     const int4 *pieces;
 };
 
@@ -62,7 +62,6 @@ struct ReduceArgs {
     const float4 *qpts;
     const ClusterDesc *cdesc;  // per pair: query points [pt_base, pt_base + n)
     SlotMap map;
-    unsigned int *ticket;      // pair-pass ticket, reset here for the next pass
     const double *W;
     const double *D;
     const float *S;

@@ -42,6 +42,20 @@ __device__ __forceinline__ void wave_sync()
 
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Wave-uniform floating values kept in scalar registers.
+__device__ __forceinline__ float uniform_f(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+__device__ __forceinline__ double uniform_d(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Membership of (x, z) in the pair set, decided exactly as the set is defined:
 // z'_r = ((R_r0 z0 + R_r1 z1) + R_r2 z2) + t_r, d = x - z',
 // s = (dx dx + dy dy) + dz dz, member iff s <= rc2; every operation is a
@@ -66,10 +80,11 @@ __device__ __noinline__ bool canonical_member(const double *T, float x0, float x
 }
 
 // Cells [i0, i1] along one axis covering [c - R, c + R]; false if none.
-__device__ __forceinline__ bool axis_range(double c, double R, double o, double h, int n, int &i0, int &i1)
+// Uses the same floor((p - o) * inv_h) as the binning.
+__device__ __forceinline__ bool axis_range(double c, double R, double o, double inv_h, int n, int &i0, int &i1)
 {
-    const double f0 = floor(((c - R) - o) / h);
-    const double f1 = floor(((c + R) - o) / h);
+    const double f0 = floor(((c - R) - o) * inv_h);
+    const double f1 = floor(((c + R) - o) * inv_h);
     if (!(f1 >= 0.0) || !(f0 <= (double)(n - 1))) return false;
     i0 = (int)fmax(f0, 0.0);
     i1 = (int)fmin(f1, (double)(n - 1));
@@ -95,11 +110,12 @@ __device__ __forceinline__ Neighbourhood neighbourhood(const double *Pm, const d
     nb.ix0 = 0; nb.ix1 = gd.nx - 1; nb.iy0 = 0; nb.iy1 = gd.ny - 1; nb.iz0 = 0; nb.iz1 = gd.nz - 1;
     nb.any = gd.n > 0;
     if (cut && nb.any)
-        nb.any = axis_range(nb.cx, nb.Rm, gd.ox, gd.h, gd.nx, nb.ix0, nb.ix1) &&
-                 axis_range(nb.cy, nb.Rm, gd.oy, gd.h, gd.ny, nb.iy0, nb.iy1) &&
-                 axis_range(nb.cz, nb.Rm, gd.oz, gd.h, gd.nz, nb.iz0, nb.iz1);
+        nb.any = axis_range(nb.cx, nb.Rm, gd.ox, gd.inv_h, gd.nx, nb.ix0, nb.ix1) &&
+                 axis_range(nb.cy, nb.Rm, gd.oy, gd.inv_h, gd.ny, nb.iy0, nb.iy1) &&
+                 axis_range(nb.cz, nb.Rm, gd.oz, gd.inv_h, gd.nz, nb.iz0, nb.iz1);
     return nb;
 }
+
 
 template <int SED, int LIND, int MODE> struct PassTraits {
     static constexpr int D = SED + LIND;
@@ -129,16 +145,16 @@ void pair_pass_kernel(const PairPassArgs a)
     const float sig2 = a.sig2;
     const bool cut = isfinite(a.kappa);
 
-    for (;;) {
-        int tk = 0;
-        if (lane == 0) tk = (int)atomicAdd(a.ticket, 1u);
-        tk = wave_uniform(__shfl(tk, 0));
-        if (tk >= a.npieces) break;
+    // one piece per wave; pieces are ordered heaviest first, so the largest
+    // pieces are dispatched first and the light ones fill in behind them
+    {
+        const int tk = wave_uniform(blockIdx.x * kWavesPerBlock + wv);
+        if (tk >= a.npieces) return;
         const int4 pc = a.pieces[a.porder[tk]];
         const int c = pc.x;
         const int b = wave_uniform(a.cpair[c]);
         const PairState *st = a.state + b;
-        if (st->done) continue;
+        if (st->done || st->pause) return;
 
         const double *P = a.pose_is_inverse ? st->Tinv : st->T;
         double Pm[12];
@@ -146,14 +162,14 @@ void pair_pass_kernel(const PairPassArgs a)
         for (int k = 0; k < 12; ++k) Pm[k] = P[k];
         const double ell = st->ell;
         const double ascale = 1.4426950408889634 / (2.0 * ell * ell);  // log2(e) / (2 ell^2)
-        const double sc = sqrt(ascale);
+        const double sc = uniform_d(sqrt(ascale));
         const double rc = a.kappa * ell;
         const double rc2 = rc * rc;
         const int2 cl = a.clus[c];
         const double4 g = a.cgeo[c];
         const GridDesc gd = a.grids[b];
         const Neighbourhood nb = neighbourhood(Pm, g, rc, cut, gd);
-        const double cx = nb.cx, cy = nb.cy, cz = nb.cz;
+        const double cx = uniform_d(nb.cx), cy = uniform_d(nb.cy), cz = uniform_d(nb.cz);
 
         // thresholds in scaled units: s' <= lo is certainly in P, s' > hi is
         // certainly out; between them the FP64 definition decides.  The band
@@ -164,9 +180,9 @@ void pair_pass_kernel(const PairPassArgs a)
             const double u = 5.9604644775390625e-8;
             const double G = u * (8.0 * (4.0 * (1.0 + g.w / rc) + 3.0) + 4.0);
             const double r2s = rc2 * ascale;
-            hi = (float)(r2s * (1.0 + G));
-            lo = (float)(r2s * (1.0 - G));
-            cull2 = (float)(nb.Rm * nb.Rm * ascale);
+            hi = uniform_f((float)(r2s * (1.0 + G)));
+            lo = uniform_f((float)(r2s * (1.0 - G)));
+            cull2 = uniform_f((float)(nb.Rm * nb.Rm * ascale));
         }
 
         // query point owned by this lane; SUB sub-streams share the candidates
@@ -178,7 +194,7 @@ void pair_pass_kernel(const PairPassArgs a)
         const int SUB = kWave >> lg;
         const bool active = t < n;
         const int pq = cl.x + (active ? t : 0);
-        const float4 zq = a.qpts[pq];
+        const float4 zq = a.qpts[pq];  // (reloaded on the rare exact-recheck path)
         const double zpx = Pm[0] * zq.x + Pm[1] * zq.y + Pm[2] * zq.z + Pm[3];
         const double zpy = Pm[4] * zq.x + Pm[5] * zq.y + Pm[6] * zq.z + Pm[7];
         const double zpz = Pm[8] * zq.x + Pm[9] * zq.y + Pm[10] * zq.z + Pm[11];
@@ -186,6 +202,8 @@ void pair_pass_kernel(const PairPassArgs a)
         const float zry = (float)((zpy - cy) * sc);
         const float zrz = (float)((zpz - cz) * sc);
         float vf[VF];
+#pragma unroll
+        for (int f = 0; f < VF / 4; ++f) vf[4 * f] = vf[4 * f + 1] = vf[4 * f + 2] = vf[4 * f + 3] = 0.0f;
 #pragma unroll
         for (int f = 0; f < F4; ++f) {
             const float4 v4 = reinterpret_cast<const float4 *>(a.qfeat)[(long long)pq * F4 + f];
@@ -203,7 +221,10 @@ void pair_pass_kernel(const PairPassArgs a)
 #pragma unroll
         for (int k = 0; k < (MODE == 1 ? VF : 1); ++k) Gf[k] = 0.0;
 
+        // W and D are summed in FP32 over one queue flush (at most kQueueCap
+        // terms per lane) and added to the FP64 accumulators after it.
         auto process = [&](int qn) {
+            float w32 = 0.f, dx32 = 0.f, dy32 = 0.f, dz32 = 0.f;
             for (int k = qs; k < qn; k += SUB) {
                 const float4 e = s_xyz[wv][k];
                 const float dx = e.x - zrx, dy = e.y - zry, dz = e.z - zrz;
@@ -212,9 +233,10 @@ void pair_pass_kernel(const PairPassArgs a)
                     bool pass = true;
                     if (s > lo) {
                         const float4 rp = a.rpts[s_src[wv][k]];
+                        const float4 zq2 = a.qpts[pq];
                         pass = a.pose_is_inverse
-                                   ? canonical_member(st->T, zq.x, zq.y, zq.z, rp.x, rp.y, rp.z, rc2)
-                                   : canonical_member(st->T, rp.x, rp.y, rp.z, zq.x, zq.y, zq.z, rc2);
+                                   ? canonical_member(st->T, zq2.x, zq2.y, zq2.z, rp.x, rp.y, rp.z, rc2)
+                                   : canonical_member(st->T, rp.x, rp.y, rp.z, zq2.x, zq2.y, zq2.z, rc2);
                     }
                     if (pass) {
                         float E = s;
@@ -236,11 +258,11 @@ void pair_pass_kernel(const PairPassArgs a)
                         }
                         const float wnl = sig2 * __builtin_amdgcn_exp2f(-E);
                         const float w = (LIND > 0) ? wnl * lin : wnl;
-                        W += (double)w;
+                        w32 += w;
                         const float wx = w * dx, wy = w * dy, wz = w * dz;
-                        Dx += (double)wx;
-                        Dy += (double)wy;
-                        Dz += (double)wz;
+                        dx32 += wx;
+                        dy32 += wy;
+                        dz32 += wz;
                         cnt += 1;
                         if (MODE == 0) {
                             S00 = fmaf(wx, dx, S00);
@@ -266,6 +288,10 @@ void pair_pass_kernel(const PairPassArgs a)
                     }
                 }
             }
+            W += (double)w32;
+            Dx += (double)dx32;
+            Dy += (double)dy32;
+            Dz += (double)dz32;
         };
 
         // this piece covers candidates [c0, c1) of the concatenated rows
@@ -446,6 +472,23 @@ __global__ void plan_slots(int4 *pieces, const int *tbase, int npieces)
         pieces[i].w = tbase[i];
 }
 
+__global__ void plan_qmap(const int2 *clus, const int2 *cpieces, const int4 *pieces, int nclus, int4 *qmap)
+{
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nclus; c += gridDim.x * blockDim.x) {
+        const int2 cl = clus[c];
+        const int2 cp = cpieces[c];
+        const int slot0 = pieces[cp.x].w;
+        for (int t = 0; t < cl.y; ++t) qmap[cl.x + t] = make_int4(t, cp.x, cp.y, slot0 + t);
+    }
+}
+
+void launch_plan_qmap(const int2 *clus, const int2 *cpieces, const int4 *pieces, int nclus, int4 *qmap,
+                      hipStream_t s)
+{
+    const int nb = std::max(1, std::min(4096, (nclus + 255) / 256));
+    hipLaunchKernelGGL(plan_qmap, dim3(nb), dim3(256), 0, s, clus, cpieces, pieces, nclus, qmap);
+}
+
 void launch_plan_count(const PairPassArgs &a, int work, int *npieces, int *cmax, long long *ccount, hipStream_t s)
 {
     const int nb = std::max(1, std::min(4096, (a.nclus + 255) / 256));
@@ -482,19 +525,21 @@ bool pair_layout_supported(int sed, int lind)
     return false;
 }
 
+template <int S, int L, int MODE>
+static void launch_one(const PairPassArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL((pair_pass_kernel<S, L, MODE>), dim3((a.npieces + kWavesPerBlock - 1) / kWavesPerBlock),
+                       dim3(kWave * kWavesPerBlock), 0, s, a);
+}
+
 bool launch_pair_pass(const PairPassArgs &a, const FeatLayout &lay, int mode, hipStream_t s)
 {
     if (a.npieces <= 0) return true;
-    // persistent waves: enough to fill the chip several times over, never
-    // more than there are pieces
-    const int blocks = std::max(1, std::min((a.npieces + kWavesPerBlock - 1) / kWavesPerBlock, 256 * 8));
-    const dim3 grid(blocks);
-    const dim3 block(kWave * kWavesPerBlock);
-#define CVO_LAUNCH(S, L)                                                                  \
-    if (lay.sed == S && lay.lind == L) {                                                  \
-        if (mode == 0) hipLaunchKernelGGL((pair_pass_kernel<S, L, 0>), grid, block, 0, s, a); \
-        else hipLaunchKernelGGL((pair_pass_kernel<S, L, 1>), grid, block, 0, s, a);           \
-        return true;                                                                      \
+#define CVO_LAUNCH(S, L)                                          \
+    if (lay.sed == S && lay.lind == L) {                          \
+        if (mode == 0) launch_one<S, L, 0>(a, s);                 \
+        else launch_one<S, L, 1>(a, s);                           \
+        return true;                                              \
     }
     CVO_LAYOUTS(CVO_LAUNCH)
 #undef CVO_LAUNCH

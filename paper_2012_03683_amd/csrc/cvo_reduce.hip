@@ -13,9 +13,9 @@
 //              H_wv =  Z A - [D]_x /(2 ell^2),   H_vv = A
 //   tr S / ell^3 = dF/dell (cutoff held fixed), |P| = sum n_j,
 //   r_max = max_j |z'_j|.
-// The curvature along the gradient is grad^T H grad.  Each block reduces a
-// fixed slice of the queries in a fixed tree order; the last block of a pair
-// (atomic ticket) combines the block partials in block order and, in step
+// The curvature along a direction d is d^T H d.  Each block reduces a fixed
+// slice of the queries in a fixed tree order; the last block of a pair
+// (atomic ticket) combines the block partials in a fixed order and, in step
 // mode, takes the ascent step -- so results are bitwise reproducible.
 #include "cvo_launch.hpp"
 
@@ -27,34 +27,41 @@ enum {
     R_ZS = 31, R_ZZ = 34, R_END = 40
 };
 
-// Solve A x = b for the 6x6 system (Gaussian elimination, partial pivoting).
-__device__ bool solve6(const double A_in[36], const double b[6], double x[6])
+// Solve G d = g for a symmetric positive definite 6x6 G by Cholesky
+// (G = L L^T), fully unrolled so everything stays in registers; false if a
+// pivot is not positive.
+__device__ bool chol_solve6(const double G[36], const double g[6], double d[6])
 {
-    double A[6][7];
-    for (int r = 0; r < 6; ++r) {
-        for (int c = 0; c < 6; ++c) A[r][c] = A_in[6 * r + c];
-        A[r][6] = b[r];
-    }
-    for (int c = 0; c < 6; ++c) {
-        int piv = c;
-        for (int r = c + 1; r < 6; ++r)
-            if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
-        if (A[piv][c] == 0.0) return false;
-        if (piv != c)
-            for (int k = 0; k < 7; ++k) {
-                const double t = A[c][k];
-                A[c][k] = A[piv][k];
-                A[piv][k] = t;
+    double L[6][6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            double s = G[6 * i + j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+            if (i == j) {
+                if (!(s > 0.0)) return false;
+                L[i][i] = sqrt(s);
+            } else {
+                L[i][j] = s / L[j][j];
             }
-        for (int r = c + 1; r < 6; ++r) {
-            const double f = A[r][c] / A[c][c];
-            for (int k = c; k < 7; ++k) A[r][k] -= f * A[c][k];
         }
     }
-    for (int r = 5; r >= 0; --r) {
-        double s = A[r][6];
-        for (int k = r + 1; k < 6; ++k) s -= A[r][k] * x[k];
-        x[r] = s / A[r][r];
+    double y[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        double s = g[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
+        y[i] = s / L[i][i];
+    }
+#pragma unroll
+    for (int i = 5; i >= 0; --i) {
+        double s = y[i];
+#pragma unroll
+        for (int k = i + 1; k < 6; ++k) s -= L[k][i] * d[k];
+        d[i] = s / L[i][i];
     }
     return true;
 }
@@ -69,7 +76,9 @@ __device__ double quad_form(const double *tot, const double xi[6])
                               {tot[R_HVV + 1], tot[R_HVV + 3], tot[R_HVV + 4]},
                               {tot[R_HVV + 2], tot[R_HVV + 4], tot[R_HVV + 5]}};
     double q = 0.0;
+#pragma unroll
     for (int r = 0; r < 3; ++r)
+#pragma unroll
         for (int k = 0; k < 3; ++k)
             q += xi[r] * Hww[r][k] * xi[k] + 2.0 * xi[r] * tot[R_HWV + 3 * r + k] * xi[3 + k] +
                  xi[3 + r] * Hvv[r][k] * xi[3 + k];
@@ -99,43 +108,56 @@ __device__ void exp_se3(const double xi[6], double E[12])
     }
     const double Wm[3][3] = {{0.0, -w2, w1}, {w2, 0.0, -w0}, {-w1, w0, 0.0}};
     double W2[3][3];
+#pragma unroll
     for (int r = 0; r < 3; ++r)
+#pragma unroll
         for (int k = 0; k < 3; ++k) W2[r][k] = Wm[r][0] * Wm[0][k] + Wm[r][1] * Wm[1][k] + Wm[r][2] * Wm[2][k];
     double V[3][3];
+#pragma unroll
     for (int r = 0; r < 3; ++r)
+#pragma unroll
         for (int k = 0; k < 3; ++k) {
             const double I = (r == k) ? 1.0 : 0.0;
             E[4 * r + k] = I + ca * Wm[r][k] + cb * W2[r][k];
             V[r][k] = I + cb * Wm[r][k] + cc * W2[r][k];
         }
+#pragma unroll
     for (int r = 0; r < 3; ++r) E[4 * r + 3] = V[r][0] * xi[3] + V[r][1] * xi[4] + V[r][2] * xi[5];
 }
 
 __device__ void compose_left(const double E[12], double T[12])
 {
     double O[12];
+#pragma unroll
     for (int r = 0; r < 3; ++r) {
+#pragma unroll
         for (int k = 0; k < 3; ++k) O[4 * r + k] = E[4 * r] * T[k] + E[4 * r + 1] * T[4 + k] + E[4 * r + 2] * T[8 + k];
         O[4 * r + 3] = E[4 * r] * T[3] + E[4 * r + 1] * T[7] + E[4 * r + 2] * T[11] + E[4 * r + 3];
     }
+#pragma unroll
     for (int k = 0; k < 12; ++k) T[k] = O[k];
 }
 
 __device__ void invert_pose(const double T[12], double Ti[12])
 {
+#pragma unroll
     for (int r = 0; r < 3; ++r) {
+#pragma unroll
         for (int k = 0; k < 3; ++k) Ti[4 * r + k] = T[4 * k + r];
         Ti[4 * r + 3] = -(T[r] * T[3] + T[4 + r] * T[7] + T[8 + r] * T[11]);
     }
 }
 
 // Finish one pair: publish the evaluation, and in step mode take the step.
-__device__ void finalize_pair(PairState *st, const AlignConst *ac, const double *tot, double *trace,
-                              long long trace_rows, int mode)
+// Works on register copies of the state and constants (one batch of loads,
+// one batch of stores) rather than on global memory field by field.
+__device__ __forceinline__ void finalize_local(PairState &st, const AlignConst &ac, const double *tot,
+                                               double *trace, long long trace_rows, int mode)
 {
-    const double ell = st->ell;
+    const double ell = st.ell;
     const double il2 = 1.0 / (ell * ell);
     double g[6];
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
         g[k] = tot[R_OM + k] * il2;
         g[3 + k] = tot[R_V + k] * il2;
@@ -143,27 +165,28 @@ __device__ void finalize_pair(PairState *st, const AlignConst *ac, const double 
     const double curv = quad_form(tot, g);
     const double F = tot[R_F];
     const double np = tot[R_N];
-    const double ind = (ac->sqrt_nm > 0.0) ? F / ac->sqrt_nm : 0.0;
-    st->F = F;
-    st->i_theta = ind;
-    st->curv = curv;
-    st->r_max = tot[R_RMAX];
-    st->dF_dell = tot[R_TRS] / (ell * ell * ell);
-    st->n_pairs = np;
-    for (int k = 0; k < 6; ++k) st->grad[k] = g[k];
+    const double ind = (ac.sqrt_nm > 0.0) ? F / ac.sqrt_nm : 0.0;
+    st.F = F;
+    st.i_theta = ind;
+    st.curv = curv;
+    st.r_max = tot[R_RMAX];
+    st.dF_dell = tot[R_TRS] / (ell * ell * ell);
+    st.n_pairs = np;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) st.grad[k] = g[k];
     const double gn2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2] + g[3] * g[3] + g[4] * g[4] + g[5] * g[5];
-    st->gnorm = sqrt(gn2);
+    st.gnorm = sqrt(gn2);
     if (mode == 0) return;
 
     // ---- ascent step (same decision sequence as the definition it follows)
-    if (np == 0.0) { st->status = ST_NO_OVERLAP; st->done = 1; return; }
-    if (gn2 == 0.0) { st->status = ST_STATIONARY; st->done = 1; return; }
+    if (np == 0.0) { st.status = ST_NO_OVERLAP; st.done = 1; return; }
+    if (gn2 == 0.0) { st.status = ST_STATIONARY; st.done = 1; return; }
     // direction: the Riemannian gradient G^-1 g.  Kinetic-energy metric of
     // the moving cloud: G = [[tr(S) I - S + mu I, [c]_x], [[c]_x^T, I]] with
     // c = mean z', S = mean z' z'^T, mu = 1e-6 (tr S + 1e-12).
     double d[6];
-    if (ac->metric == 0) {
-        const double im = ac->inv_m;
+    if (ac.metric == 0) {
+        const double im = ac.inv_m;
         const double c[3] = {tot[R_ZS] * im, tot[R_ZS + 1] * im, tot[R_ZS + 2] * im};
         const double S[3][3] = {{tot[R_ZZ + 0] * im, tot[R_ZZ + 1] * im, tot[R_ZZ + 2] * im},
                                 {tot[R_ZZ + 1] * im, tot[R_ZZ + 3] * im, tot[R_ZZ + 4] * im},
@@ -172,15 +195,18 @@ __device__ void finalize_pair(PairState *st, const AlignConst *ac, const double 
         const double mu = 1e-6 * (trs + 1e-12);
         const double Cx[3][3] = {{0.0, -c[2], c[1]}, {c[2], 0.0, -c[0]}, {-c[1], c[0], 0.0}};
         double G[36];
+#pragma unroll
         for (int r = 0; r < 3; ++r)
+#pragma unroll
             for (int k = 0; k < 3; ++k) {
                 G[6 * r + k] = (r == k ? trs + mu : 0.0) - S[r][k];
                 G[6 * r + 3 + k] = Cx[r][k];
                 G[6 * (3 + r) + k] = Cx[k][r];
                 G[6 * (3 + r) + 3 + k] = (r == k) ? 1.0 : 0.0;
             }
-        if (!solve6(G, g, d)) { st->status = ST_STATIONARY; st->done = 1; return; }
+        if (!chol_solve6(G, g, d)) { st.status = ST_STATIONARY; st.done = 1; return; }
     } else {
+#pragma unroll
         for (int k = 0; k < 6; ++k) d[k] = g[k];
     }
     const double slope = g[0] * d[0] + g[1] * d[1] + g[2] * d[2] + g[3] * d[3] + g[4] * d[4] + g[5] * d[5];
@@ -188,15 +214,16 @@ __device__ void finalize_pair(PairState *st, const AlignConst *ac, const double 
     const double tauN = (curv_d < 0.0) ? slope / (-curv_d) : INFINITY;
     const double nw = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     const double nv = sqrt(d[3] * d[3] + d[4] * d[4] + d[5] * d[5]);
-    const double tauC = ac->step_lambda * ell / (nw * tot[R_RMAX] + nv);
+    const double tauC = ac.step_lambda * ell / (nw * tot[R_RMAX] + nv);
     const double tau = tauN < tauC ? tauN : tauC;
     double xi[6], E[12];
+#pragma unroll
     for (int k = 0; k < 6; ++k) xi[k] = tau * d[k];
     exp_se3(xi, E);
-    compose_left(E, st->T);
-    invert_pose(st->T, st->Tinv);
-    st->tau = tau;
-    const long long it = st->it;
+    compose_left(E, st.T);
+    invert_pose(st.T, st.Tinv);
+    st.tau = tau;
+    const long long it = st.it;
     if (trace && it < trace_rows) {
         double *tr = trace + it * kTraceLen;
         tr[0] = (double)it;
@@ -208,53 +235,76 @@ __device__ void finalize_pair(PairState *st, const AlignConst *ac, const double 
         tr[6] = np;
         tr[7] = curv_d;
     }
-    st->it = it + 1;
-    st->total_pairs += np;
-    if (!ac->fixed_iters) {
-        const double ip = st->i_prev;
-        if (isfinite(ip) && fabs(ind - ip) <= ac->ind_rel_tol * fabs(ind) && ell > ac->ell_min) {
-            const double e2 = ac->decay * ell;
-            st->ell = e2 > ac->ell_min ? e2 : ac->ell_min;
-            st->i_prev = NAN;
+    st.it = it + 1;
+    st.total_pairs += np;
+    if (!ac.fixed_iters) {
+        const double ip = st.i_prev;
+        if (isfinite(ip) && fabs(ind - ip) <= ac.ind_rel_tol * fabs(ind) && ell > ac.ell_min) {
+            const double e2 = ac.decay * ell;
+            st.ell = e2 > ac.ell_min ? e2 : ac.ell_min;
+            st.i_prev = NAN;
         } else {
-            st->i_prev = ind;
+            st.i_prev = ind;
         }
-        if (st->ell == ac->ell_min && tau * nw < ac->eps_rot && tau * nv < ac->eps_trans) {
-            st->status = ST_CONVERGED;
-            st->done = 1;
+        if (st.ell == ac.ell_min && tau * nw < ac.eps_rot && tau * nv < ac.eps_trans) {
+            st.status = ST_CONVERGED;
+            st.done = 1;
             return;
         }
     }
-    if (it + 1 >= ac->max_iter) {
-        st->status = ST_MAX_ITER;
-        st->done = 1;
+    if (it + 1 >= ac.max_iter) {
+        st.status = ST_MAX_ITER;
+        st.done = 1;
+        return;
     }
+    // the views no longer fit: the cutoff shrank past the rebuild ratio, or
+    // the pair density fell to a lower class.  Decided from the iterates
+    // alone, so where views change does not depend on how many iterations
+    // are enqueued between host checks.
+    if (isfinite(ac.kappa) && ac.kappa * st.ell < ac.rebuild_ratio * st.rc_build) st.pause = 1;
+    if (ac.adaptive && st.cls_built >= 0 && density_class(np * ac.inv_m) < st.cls_built) st.pause = 1;
 }
+
+__device__ void finalize_pair(PairState *st_g, const AlignConst *ac_g, const double *tot, double *trace,
+                              long long trace_rows, int mode)
+{
+    PairState st = *st_g;
+    const AlignConst ac = *ac_g;
+    finalize_local(st, ac, tot, trace, trace_rows, mode);
+    *st_g = st;
+}
+
+static_assert(kRedThreads == 256 && R_END == 40 && R_END <= kRedVals, "reduction layout");
 
 __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
 {
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && a.ticket) *a.ticket = 0u;
     const int b = blockIdx.y;
     PairState *st = a.state + b;
-    if (st->done) return;
+    if (st->done || st->pause) return;
     const ClusterDesc cd = a.cdesc[b];
     double T[12];
+#pragma unroll
     for (int k = 0; k < 12; ++k) T[k] = st->T[k];
     const double ell = st->ell;
     const double ascale = 1.4426950408889634 / (2.0 * ell * ell);
     const double isc = 1.0 / sqrt(ascale), ia = 1.0 / ascale;
     const double il2 = 1.0 / (ell * ell), il4 = il2 * il2;
 
-    double acc[kRedVals];
-    for (int k = 0; k < kRedVals; ++k) acc[k] = 0.0;
+    // every accumulator index below is a compile-time constant, so the 40
+    // values stay in registers
+    double acc[R_END];
+#pragma unroll
+    for (int k = 0; k < R_END; ++k) acc[k] = 0.0;
     const long long end = (long long)cd.pt_base + cd.n;
     for (long long j = (long long)cd.pt_base + (long long)blockIdx.x * kRedThreads + threadIdx.x; j < end;
          j += (long long)a.nblk * kRedThreads) {
         const float4 zq = a.qpts[j];
+        const int4 qm = a.map.qmap[j];
         const double z[3] = {T[0] * zq.x + T[1] * zq.y + T[2] * zq.z + T[3],
                              T[4] * zq.x + T[5] * zq.y + T[6] * zq.z + T[7],
                              T[8] * zq.x + T[9] * zq.y + T[10] * zq.z + T[11]};
         acc[R_RMAX] = fmax(acc[R_RMAX], sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]));
+#pragma unroll
         for (int k = 0; k < 3; ++k) acc[R_ZS + k] += z[k];
         acc[R_ZZ + 0] += z[0] * z[0];
         acc[R_ZZ + 1] += z[0] * z[1];
@@ -263,25 +313,32 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
         acc[R_ZZ + 4] += z[1] * z[2];
         acc[R_ZZ + 5] += z[2] * z[2];
         // combine this query's partial moments over its cluster's pieces
-        const int c = a.map.tclus[j];
-        const int t = (int)(j - a.map.clus[c].x);
-        const int2 cp = a.map.cpieces[c];
         int nj = 0;
-        double Wt = 0.0, Dsum[3] = {0.0, 0.0, 0.0}, Ssum[6] = {0, 0, 0, 0, 0, 0};
-        for (int i = cp.x; i < cp.x + cp.y; ++i) {
-            const long long o = (long long)a.map.pieces[i].w + t;
+        double Wt = 0.0, D0 = 0.0, D1 = 0.0, D2 = 0.0;
+        double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0, S5 = 0.0;
+        for (int i = qm.y; i < qm.y + qm.z; ++i) {
+            const long long o = (i == qm.y) ? (long long)qm.w : (long long)a.map.pieces[i].w + qm.x;
             nj += a.cnt[o];
             Wt += a.W[o];
-            for (int k = 0; k < 3; ++k) Dsum[k] += a.D[3 * o + k];
-            for (int k = 0; k < 6; ++k) Ssum[k] += (double)a.S[6 * o + k];
+            D0 += a.D[3 * o + 0];
+            D1 += a.D[3 * o + 1];
+            D2 += a.D[3 * o + 2];
+            const float *So = a.S + 6 * o;
+            S0 += (double)So[0];
+            S1 += (double)So[1];
+            S2 += (double)So[2];
+            S3 += (double)So[3];
+            S4 += (double)So[4];
+            S5 += (double)So[5];
         }
         if (nj == 0) continue;
-        const double Dt[3] = {Dsum[0] * isc, Dsum[1] * isc, Dsum[2] * isc};
-        const double S6[6] = {Ssum[0] * ia, Ssum[1] * ia, Ssum[2] * ia, Ssum[3] * ia, Ssum[4] * ia, Ssum[5] * ia};
+        const double Dt[3] = {D0 * isc, D1 * isc, D2 * isc};
+        const double S6[6] = {S0 * ia, S1 * ia, S2 * ia, S3 * ia, S4 * ia, S5 * ia};
         acc[R_F] += Wt;
         acc[R_OM + 0] += z[1] * Dt[2] - z[2] * Dt[1];
         acc[R_OM + 1] += z[2] * Dt[0] - z[0] * Dt[2];
         acc[R_OM + 2] += z[0] * Dt[1] - z[1] * Dt[0];
+#pragma unroll
         for (int k = 0; k < 3; ++k) acc[R_V + k] += Dt[k];
         acc[R_TRS] += S6[0] + S6[3] + S6[5];
         acc[R_N] += (double)nj;
@@ -291,70 +348,107 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
                                 {S6[2] * il4, S6[4] * il4, S6[5] * il4 - Wt * il2}};
         const double Zm[3][3] = {{0.0, -z[2], z[1]}, {z[2], 0.0, -z[0]}, {-z[1], z[0], 0.0}};
         double ZA[3][3];
+#pragma unroll
         for (int r = 0; r < 3; ++r)
+#pragma unroll
             for (int k = 0; k < 3; ++k) ZA[r][k] = Zm[r][0] * A[0][k] + Zm[r][1] * A[1][k] + Zm[r][2] * A[2][k];
         const double dz = Dt[0] * z[0] + Dt[1] * z[1] + Dt[2] * z[2];
-        const int ur[6] = {0, 0, 0, 1, 1, 2}, uc[6] = {0, 1, 2, 1, 2, 2};
+        // upper triangle (r, k) of the symmetric 3x3 blocks, slot q
+#pragma unroll
         for (int q = 0; q < 6; ++q) {
-            const int r = ur[q], k = uc[q];
+            const int r = (q < 3) ? 0 : (q < 5 ? 1 : 2);
+            const int k = (q < 3) ? q : (q < 5 ? q - 2 : 2);
             const double zaz = ZA[r][0] * Zm[0][k] + ZA[r][1] * Zm[1][k] + ZA[r][2] * Zm[2][k];
             const double m3 = 0.5 * (Dt[r] * z[k] + z[r] * Dt[k]) - (r == k ? dz : 0.0);
             acc[R_HWW + q] += -zaz + m3 * il2;
             acc[R_HVV + q] += A[r][k];
         }
         const double Dx[3][3] = {{0.0, -Dt[2], Dt[1]}, {Dt[2], 0.0, -Dt[0]}, {-Dt[1], Dt[0], 0.0}};
+#pragma unroll
         for (int r = 0; r < 3; ++r)
+#pragma unroll
             for (int k = 0; k < 3; ++k) acc[R_HWV + 3 * r + k] += ZA[r][k] - 0.5 * Dx[r][k] * il2;
     }
 
-    // block reduction: lanes (xor tree), then waves in order
-    for (int k = 0; k < R_END; ++k) {
-        double v = acc[k];
-        for (int off = kWave / 2; off > 0; off >>= 1) {
-            const double o = __shfl_xor(v, off);
-            v = (k == R_RMAX) ? fmax(v, o) : v + o;
-        }
-        acc[k] = v;
-    }
-    __shared__ double red[kRedThreads / kWave][kRedVals];
+    // block reduction, 20 values at a time through LDS: every thread stores
+    // its 20 values; thread (value kv = t / 8, stripe s = t % 8), t < 160,
+    // adds the entries s, s + 8, ... of its value, and an 8-lane shuffle tree
+    // finishes.  Fixed order throughout.
+    constexpr int kChunk = 20, kStripes = 8;
+    __shared__ double red[kChunk][kRedThreads];
+    __shared__ double tot[R_END];
     __shared__ int s_last;
-    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-    if (lane == 0)
-        for (int k = 0; k < R_END; ++k) red[wv][k] = acc[k];
-    __syncthreads();
+    const int tid = threadIdx.x;
     double *part = a.partials + ((long long)b * a.nblk + blockIdx.x) * kRedVals;
-    if (threadIdx.x < R_END) {
-        double v = red[0][threadIdx.x];
-        for (int w = 1; w < kRedThreads / kWave; ++w)
-            v = (threadIdx.x == R_RMAX) ? fmax(v, red[w][threadIdx.x]) : v + red[w][threadIdx.x];
-        part[threadIdx.x] = v;
+    {
+        const int kv = tid / kStripes, sl = tid % kStripes;
+#pragma unroll
+        for (int c = 0; c < R_END / kChunk; ++c) {
+#pragma unroll
+            for (int k = 0; k < kChunk; ++k) red[k][tid] = acc[kChunk * c + k];
+            __syncthreads();
+            if (kv < kChunk) {
+                const bool mx = (kChunk * c + kv) == R_RMAX;
+                double v = red[kv][sl];
+#pragma unroll
+                for (int m = 1; m < kRedThreads / kStripes; ++m) {
+                    const double o = red[kv][sl + kStripes * m];
+                    v = mx ? fmax(v, o) : v + o;
+                }
+#pragma unroll
+                for (int off = kStripes / 2; off > 0; off >>= 1) {
+                    const double o = __shfl_xor(v, off);
+                    v = mx ? fmax(v, o) : v + o;
+                }
+                if (sl == 0) part[kChunk * c + kv] = v;
+            }
+            __syncthreads();
+        }
     }
     __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         const unsigned int ticket = atomicAdd(&a.counters[b], 1u);
         s_last = (ticket == (unsigned int)(a.nblk - 1));
     }
     __syncthreads();
     if (!s_last) return;
     __threadfence();
-    // gather every block partial of this pair at once (one round of loads),
-    // then combine each value over the blocks in block order
-    __shared__ double tot[kRedVals];
-    __shared__ double parts[64 * kRedVals];
+
+    // last block: thread (kv = t / 32, stripe sl = t % 32) adds blocks sl,
+    // sl + 32, ... of the values kv + 8 c, four stripes' loads in flight at
+    // once; a 32-lane shuffle tree finishes.  Fixed order throughout.
+    const int kv = tid >> 5, sl = tid & 31;
     const double *pb = a.partials + (long long)b * a.nblk * kRedVals;
-    for (int k = threadIdx.x; k < a.nblk * kRedVals; k += kRedThreads) parts[k] = pb[k];
-    __syncthreads();
-    if (threadIdx.x < R_END) {
-        double v = 0.0;
-        for (int k = 0; k < a.nblk; ++k) {
-            const double p = parts[k * kRedVals + threadIdx.x];
-            v = (threadIdx.x == R_RMAX) ? fmax(v, p) : v + p;
+    double v[R_END / 8];
+#pragma unroll
+    for (int c = 0; c < R_END / 8; ++c) v[c] = 0.0;
+    for (int q0 = sl; q0 < a.nblk; q0 += 4 * 32) {
+        double p[4][R_END / 8];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = q0 + 32 * u;
+#pragma unroll
+            for (int c = 0; c < R_END / 8; ++c) p[u][c] = (q < a.nblk) ? pb[(long long)q * kRedVals + 8 * c + kv] : 0.0;
         }
-        tot[threadIdx.x] = v;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < R_END / 8; ++c)
+                v[c] = ((8 * c + kv) == R_RMAX) ? fmax(v[c], p[u][c]) : v[c] + p[u][c];
+    }
+#pragma unroll
+    for (int c = 0; c < R_END / 8; ++c) {
+        const bool mx = (8 * c + kv) == R_RMAX;
+        double x = v[c];
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) {
+            const double o = __shfl_xor(x, off);
+            x = mx ? fmax(x, o) : x + o;
+        }
+        if (sl == 0) tot[8 * c + kv] = x;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         a.counters[b] = 0u;
         finalize_pair(st, a.ac + b, tot, a.trace ? a.trace + (long long)b * a.trace_rows * kTraceLen : nullptr,
                       a.trace_rows, a.mode);
@@ -380,9 +474,9 @@ __global__ void backward_finish(const BackwardArgs a)
     for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < a.n;
          p += (long long)gridDim.x * blockDim.x) {
         const long long o = a.qperm[p];
-        const int c = a.map.tclus[p];
-        const int t = (int)(p - a.map.clus[c].x);
-        const int2 cp = a.map.cpieces[c];
+        const int4 qm = a.map.qmap[p];
+        const int t = qm.x;
+        const int2 cp = make_int2(qm.y, qm.z);
         if (a.dxyz) {
             double d0 = 0.0, d1 = 0.0, d2 = 0.0;
             for (int i = cp.x; i < cp.x + cp.y; ++i) {

@@ -50,7 +50,7 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(cvo.cvo_align_params) == 9 * 8 + 8 + 8
     assert ctypes.sizeof(cvo.cvo_align_report) == 56
     assert ctypes.sizeof(cvo.cvo_eval) == 8 * 12
-    assert ctypes.sizeof(cvo.cvo_tuning) == 40
+    assert ctypes.sizeof(cvo.cvo_tuning) == 48
 
 
 def test_product_path_refuses_cpu_tensors():
