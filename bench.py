@@ -16,10 +16,16 @@ Printed JSON line:
   extra      registrations/s, the batched form vs a loop of plain calls, the
              backward form
 Inputs are resident in device memory before the timed region starts.
+
+roofline.traffic is the pair-pass kernel's HBM bytes per launch from
+rocprofv3 FETCH_SIZE / WRITE_SIZE counters (profiles/pair_pass_traffic.json,
+scaled by the same counters read on a plain copy: `--copy-calibration`); it is
+null when the kernel source has changed since the counters were taken.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -39,6 +45,43 @@ def ops_per_pair(n_se, n_lin):
     return 31 + 2 * n_se + (n_lin + 1 if n_lin else 0)
 
 
+KERNEL_SOURCES = ("paper_2012_03683_amd/csrc/cvo_pairs.hip", "paper_2012_03683_amd/csrc/cvo_internal.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pair_pass_traffic.json")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per pair-pass launch from the committed counter summary, or
+    None when it is missing or was taken on another version of the kernel."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def copy_calibration(nbytes=256 << 20, reps=5):
+    """A plain device-to-device copy of known size, for scaling the HBM
+    byte counters (run under rocprofv3 --pmc)."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").uniform_()
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -46,10 +89,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import torch
     import paper_2012_03683_amd as cvo
@@ -102,7 +150,7 @@ def main():
     Eerr = np.linalg.inv(p.T_gt) @ T_last
     rot_err = float(np.degrees(np.arccos(np.clip((np.trace(Eerr[:3, :3]) - 1) / 2, -1, 1))))
     out = {
-        "metric": "kernel-pair evals/s (F + se(3) gradient), full registrations, 1 MI355X",
+        "metric": "kernel-pair evals/s + registrations/s (F+se(3) grad) vs plain path, 1 MI355X",
         "value": value,
         "unit": "pair-evals/s",
         "n_gpus": 1,
@@ -134,7 +182,7 @@ def main():
             "peak": PEAK_SLOTS / 1e12,
             "unit": "T lane-ops/s",
             "frac": achieved / PEAK_SLOTS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "kernel": "pair_pass_kernel<5,19,0>",
             "ops_per_pair": opp,
             "avg_launch_ms": tim["pair_ms"] / max(tim["pair_launches"], 1),

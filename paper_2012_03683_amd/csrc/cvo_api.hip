@@ -60,7 +60,7 @@ struct cvo_context {
     std::map<std::string, Buf> bufs;
     void *pinned = nullptr;
     size_t pinned_cap = 0;
-    cvo_tuning tuning{16, 1.0, 0.5, 0.6, 16, 16384, 1};
+    cvo_tuning tuning{16, 1.0, 0.5, 0.6, 16, 8192, 1};
     bool profiling = false;
     cvo_timing timing{0, 0.0, 0, 0};
     std::vector<hipEvent_t> ev_free;
@@ -567,7 +567,7 @@ ClusterView build_clusters(cvo_context *ctx, const std::string &pre, const std::
 // `piece_work` query x candidate products (planned at the pose in the device
 // state), and the pieces are processed heaviest first.
 struct Plan {
-    int4 *qmap = nullptr;   // per query: (t, first piece, pieces, first slot)
+    int4 *qmap = nullptr;   // per query: (t, cluster size, pieces, first slot)
     int4 *pieces = nullptr;
     int *porder = nullptr;
     int2 *cpieces = nullptr;
@@ -686,12 +686,10 @@ PairPassArgs pass_args(const ClusterView &q, const GridView &r, const PairState 
     return a;
 }
 
-SlotMap slot_map(const ClusterView &q, const Plan &pl)
+SlotMap slot_map(const Plan &pl)
 {
     SlotMap m;
     m.qmap = pl.qmap;
-    m.pieces = pl.pieces;
-    (void)q;
     return m;
 }
 
@@ -713,6 +711,8 @@ void run_pair_pass(cvo_context *ctx, const PairPassArgs &a, const FeatLayout &la
     ctx->timing.evaluations += 1;
 }
 
+// Blocks per pair of the reduction: one thread per query point, up to 512
+// blocks.
 int reduce_blocks(const std::vector<ClusterDesc> &cd)
 {
     long long mx = 1;
@@ -768,6 +768,8 @@ void build_views(cvo_context *ctx, Problem &p, const std::vector<CloudPtrs> &X, 
     p.clus = build_clusters(ctx, "fz", Z, rc, p.lay, shape);
     p.plan = make_plan(ctx, "fp", p.clus, p.grid, p.d_state, 0, p.kappa);
     p.mom = moments(ctx, "fm", p.plan.nslots, p.lay.d4, false);
+    p.nblk = reduce_blocks(p.clus.desc);
+    p.partials = ctx->get_t<double>("partials", shape.size() * (size_t)p.nblk * kRedVals);
 }
 
 void setup_problem(cvo_context *ctx, Problem &p, const std::vector<CloudPtrs> &X, const std::vector<CloudPtrs> &Z,
@@ -781,8 +783,6 @@ void setup_problem(cvo_context *ctx, Problem &p, const std::vector<CloudPtrs> &X
     build_views(ctx, p, X, Z, ell, std::vector<ViewShape>(B, fixed_shape(ctx)));
     p.d_ac = ctx->get_t<AlignConst>("aconst", B);
     ctx->upload(p.d_ac, ac.data(), sizeof(AlignConst) * B);
-    p.nblk = reduce_blocks(p.clus.desc);
-    p.partials = ctx->get_t<double>("partials", (size_t)B * p.nblk * kRedVals);
     p.counters = ctx->get_t<unsigned int>("counters", B);
     HIP_OK(hipMemsetAsync(p.counters, 0, sizeof(unsigned int) * B, ctx->stream));
 }
@@ -795,7 +795,7 @@ void iteration_args(const Problem &p, int mode, double *trace, long long trace_r
     std::memset(&r, 0, sizeof(r));
     r.qpts = p.clus.pts;
     r.cdesc = p.clus.d_desc;
-    r.map = slot_map(p.clus, p.plan);
+    r.map = slot_map(p.plan);
     r.W = p.mom.W;
     r.D = p.mom.D;
     r.S = p.mom.S;
@@ -1260,7 +1260,7 @@ cvo_status cvo_inner_product_backward(cvo_handle h, const cvo_cloud *X, const cv
             run_pair_pass(h, a, lay, 1);
             BackwardArgs ba;
             std::memset(&ba, 0, sizeof(ba));
-            ba.map = slot_map(cz, pl);
+            ba.map = slot_map(pl);
             ba.qperm = cz.perm;
             ba.D = m.D;
             ba.G = m.G;
@@ -1292,7 +1292,7 @@ cvo_status cvo_inner_product_backward(cvo_handle h, const cvo_cloud *X, const cv
             run_pair_pass(h, a, lay, 1);
             BackwardArgs ba;
             std::memset(&ba, 0, sizeof(ba));
-            ba.map = slot_map(cx, pl);
+            ba.map = slot_map(pl);
             ba.qperm = cx.perm;
             ba.D = m.D;
             ba.G = m.G;

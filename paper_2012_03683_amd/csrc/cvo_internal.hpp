@@ -24,7 +24,7 @@
 namespace cvo {
 
 constexpr int kWave = 64;
-constexpr int kWavesPerBlock = 4;
+constexpr int kWavesPerBlock = 1;  // pair pass: one wave per workgroup, so a finished piece frees its slot at once
 constexpr int kQueueCap = 80;    // LDS candidate queue per wave
 constexpr int kQueueFlush = 16;  // process the queue once it holds this many (cap >= flush + 64)
 constexpr int kTraceLen = 8;

@@ -49,13 +49,13 @@ void launch_plan_slots(int4 *pieces, const int *tbase, int npieces, hipStream_t 
 void launch_plan_qmap(const int2 *clus, const int2 *cpieces, const int4 *pieces, int nclus, int4 *qmap,
                       hipStream_t s);
 
-// Where a query's partial moments live: qmap[j] = (t, first piece, number of
-// pieces, slot in the first piece) for query j at position t of its cluster;
-// piece i keeps the partial at slot pieces[i].w + t.  Partials are combined
-// in piece order.
+
+// Where a query's partial moments live: qmap[j] = (t, n, np, s0) for query j
+// at position t of a cluster of n queries cut into np pieces; the cluster's
+// pieces own consecutive blocks of n output slots, so the query's partial of
+// piece k is at slot s0 + k n.  Partials are combined in piece order.
 struct SlotMap {
     const int4 *qmap;
-    const int4 *pieces;
 };
 
 struct ReduceArgs {

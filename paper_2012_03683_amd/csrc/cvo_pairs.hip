@@ -478,7 +478,7 @@ __global__ void plan_qmap(const int2 *clus, const int2 *cpieces, const int4 *pie
         const int2 cl = clus[c];
         const int2 cp = cpieces[c];
         const int slot0 = pieces[cp.x].w;
-        for (int t = 0; t < cl.y; ++t) qmap[cl.x + t] = make_int4(t, cp.x, cp.y, slot0 + t);
+        for (int t = 0; t < cl.y; ++t) qmap[cl.x + t] = make_int4(t, cl.y, cp.y, slot0 + t);
     }
 }
 

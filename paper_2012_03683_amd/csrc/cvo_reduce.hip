@@ -3,7 +3,8 @@
 // lengthscale annealed as in Sec. IV).
 //
 // From the per-query moments W_j = sum_i w_ij, D_j = sum_i w_ij d_ij and
-// S_j = sum_i w_ij d_ij d_ij^T (d = x - z'), one O(M) pass gives
+// S_j = sum_i w_ij d_ij d_ij^T (d = x - z'), held as partial moments per
+// piece of the query's candidate list, one O(M) pass gives
 //   F        = sum_j W_j                                       (eq. (7))
 //   omega    = ell^-2 sum_j z'_j x D_j,  v = ell^-2 sum_j D_j   (gradient)
 //   H        = sum_j H_j, the 6x6 matrix with xi^T H xi equal to the second
@@ -299,7 +300,7 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
     for (long long j = (long long)cd.pt_base + (long long)blockIdx.x * kRedThreads + threadIdx.x; j < end;
          j += (long long)a.nblk * kRedThreads) {
         const float4 zq = a.qpts[j];
-        const int4 qm = a.map.qmap[j];
+        const int4 qm = a.map.qmap[j];  // (t, cluster size, pieces, first slot)
         const double z[3] = {T[0] * zq.x + T[1] * zq.y + T[2] * zq.z + T[3],
                              T[4] * zq.x + T[5] * zq.y + T[6] * zq.z + T[7],
                              T[8] * zq.x + T[9] * zq.y + T[10] * zq.z + T[11]};
@@ -312,24 +313,42 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
         acc[R_ZZ + 3] += z[1] * z[1];
         acc[R_ZZ + 4] += z[1] * z[2];
         acc[R_ZZ + 5] += z[2] * z[2];
-        // combine this query's partial moments over its cluster's pieces
+        // the query's partial moments of its cluster's pieces, in piece
+        // order: piece k's is at slot first + k n, so the loads of four
+        // pieces are independent and in flight together
         int nj = 0;
         double Wt = 0.0, D0 = 0.0, D1 = 0.0, D2 = 0.0;
         double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0, S5 = 0.0;
-        for (int i = qm.y; i < qm.y + qm.z; ++i) {
-            const long long o = (i == qm.y) ? (long long)qm.w : (long long)a.map.pieces[i].w + qm.x;
-            nj += a.cnt[o];
-            Wt += a.W[o];
-            D0 += a.D[3 * o + 0];
-            D1 += a.D[3 * o + 1];
-            D2 += a.D[3 * o + 2];
-            const float *So = a.S + 6 * o;
-            S0 += (double)So[0];
-            S1 += (double)So[1];
-            S2 += (double)So[2];
-            S3 += (double)So[3];
-            S4 += (double)So[4];
-            S5 += (double)So[5];
+        constexpr int kU = 4;
+        for (int k0 = 0; k0 < qm.z; k0 += kU) {
+            int c[kU];
+            double w[kU], d[kU][3];
+            float sv[kU][6];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const bool ok = k0 + u < qm.z;
+                const long long o = (long long)qm.w + (long long)(k0 + u) * qm.y;
+                c[u] = ok ? a.cnt[o] : 0;
+                w[u] = ok ? a.W[o] : 0.0;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) d[u][q] = ok ? a.D[3 * o + q] : 0.0;
+#pragma unroll
+                for (int q = 0; q < 6; ++q) sv[u][q] = ok ? a.S[6 * o + q] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                nj += c[u];
+                Wt += w[u];
+                D0 += d[u][0];
+                D1 += d[u][1];
+                D2 += d[u][2];
+                S0 += (double)sv[u][0];
+                S1 += (double)sv[u][1];
+                S2 += (double)sv[u][2];
+                S3 += (double)sv[u][3];
+                S4 += (double)sv[u][4];
+                S5 += (double)sv[u][5];
+            }
         }
         if (nj == 0) continue;
         const double Dt[3] = {D0 * isc, D1 * isc, D2 * isc};
@@ -474,13 +493,11 @@ __global__ void backward_finish(const BackwardArgs a)
     for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < a.n;
          p += (long long)gridDim.x * blockDim.x) {
         const long long o = a.qperm[p];
-        const int4 qm = a.map.qmap[p];
-        const int t = qm.x;
-        const int2 cp = make_int2(qm.y, qm.z);
+        const int4 qm = a.map.qmap[p];  // (t, cluster size, pieces, first slot)
         if (a.dxyz) {
             double d0 = 0.0, d1 = 0.0, d2 = 0.0;
-            for (int i = cp.x; i < cp.x + cp.y; ++i) {
-                const long long s = (long long)a.map.pieces[i].w + t;
+            for (int k = 0; k < qm.z; ++k) {
+                const long long s = (long long)qm.w + (long long)k * qm.y;
                 d0 += a.D[3 * s];
                 d1 += a.D[3 * s + 1];
                 d2 += a.D[3 * s + 2];
@@ -493,8 +510,8 @@ __global__ void backward_finish(const BackwardArgs a)
                 const int col = a.lay.col[k];
                 if (col < 0) continue;
                 double gk = 0.0;
-                for (int i = cp.x; i < cp.x + cp.y; ++i)
-                    gk += a.G[((long long)a.map.pieces[i].w + t) * a.lay.d4 + k];
+                for (int i = 0; i < qm.z; ++i)
+                    gk += a.G[((long long)qm.w + (long long)i * qm.y) * a.lay.d4 + k];
                 a.dfeat[o * a.lay.src_dim + col] = (float)(a.gF * gk * a.lay.gscale[k]);
             }
         }
