@@ -151,10 +151,11 @@ typedef struct {
     double rebuild_ratio;  /* rebuild grids when cutoff < rebuild_ratio * cutoff at build, in (0, 1] */
     int32_t unroll;        /* iterations enqueued per host check / per captured graph, 1..64 */
     int32_t piece_work;    /* query x candidate products per unit of pair-pass work, 256..2^24 */
-    int32_t adaptive;      /* 0 or 1.  1: a registration re-chooses cluster_max and cell_factor at every
-                            * grid build from the in-cutoff pairs per query point of its latest iteration
-                            * (>= 2000: 64 and 0.5; >= 500: 32 and 0.5; fewer, or not yet measured: the
-                            * two fields above).  One-shot calls always use the fields above. */
+    int32_t adaptive;      /* 0 or 1.  1: a registration re-chooses cluster_max, cell_factor and
+                            * cluster_factor at every view build from the in-cutoff pairs per query point
+                            * of its latest iteration: >= 2000: 64, 0.5, 0.5; >= 500: 32, 0.5, 0.5;
+                            * >= 100: 32, 1.0, 1.5; fewer: 16, 1.0, 1.5; not yet measured: the three
+                            * fields above.  One-shot calls always use the fields above. */
 } cvo_tuning;
 
 /* Per-handle timing of the dominant kernel, measured with HIP events on the

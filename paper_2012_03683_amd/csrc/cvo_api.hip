@@ -347,26 +347,38 @@ std::vector<float> cloud_boxes(cvo_context *ctx, const std::string &pre, const s
     return box;
 }
 
-// Shape of the views of one pair: query points per cluster and grid cell edge
-// relative to the cutoff radius.
+// Shape of the views of one pair: query points per cluster, grid cell edge
+// and cluster edge cap, both relative to the cutoff radius.
 struct ViewShape {
     int cluster_max;
     double cell_factor;
-    bool operator==(const ViewShape &o) const { return cluster_max == o.cluster_max && cell_factor == o.cell_factor; }
+    double cluster_factor;
+    bool operator==(const ViewShape &o) const
+    {
+        return cluster_max == o.cluster_max && cell_factor == o.cell_factor && cluster_factor == o.cluster_factor;
+    }
 };
 
-ViewShape fixed_shape(const cvo_context *ctx) { return ViewShape{ctx->tuning.cluster_max, ctx->tuning.cell_factor}; }
+ViewShape fixed_shape(const cvo_context *ctx)
+{
+    return ViewShape{ctx->tuning.cluster_max, ctx->tuning.cell_factor, ctx->tuning.cluster_factor};
+}
 
 // Shape for a density class (density_class of the in-cutoff pairs per query
 // point; -1 when unknown).  Dense bands amortise each candidate load over
-// more queries and cut the neighbourhood finer; sparse bands keep clusters
-// small.
+// more queries and cut the neighbourhood finer; sparse bands, where a
+// cluster holds a few points, let clusters grow to 1.5 cutoff radii so a
+// wave's fixed cost is shared by more queries.
 ViewShape density_shape(const cvo_context *ctx, int cls)
 {
     if (!ctx->tuning.adaptive) return fixed_shape(ctx);
-    if (cls == 2) return ViewShape{64, 0.5};
-    if (cls == 1) return ViewShape{32, 0.5};
-    return fixed_shape(ctx);
+    switch (cls) {
+    case 3: return ViewShape{64, 0.5, 0.5};
+    case 2: return ViewShape{32, 0.5, 0.5};
+    case 1: return ViewShape{32, 1.0, 1.5};
+    case 0: return ViewShape{16, 1.0, 1.5};
+    default: return fixed_shape(ctx);
+    }
 }
 
 GridView build_grid(cvo_context *ctx, const std::string &pre, const std::vector<CloudPtrs> &cl,
@@ -488,7 +500,7 @@ ClusterView build_clusters(cvo_context *ctx, const std::string &pre, const std::
             for (int k = 0; k < 3; ++k) lo[k] = box[8 * c + k];
             ext = std::max({box[8 * c + 3] - lo[0], box[8 * c + 4] - lo[1], box[8 * c + 5] - lo[2], 1e-6});
         }
-        const double cap = std::isfinite(rc[c]) ? ctx->tuning.cluster_factor * rc[c] : ext * 2.0;
+        const double cap = std::isfinite(rc[c]) ? shape[c].cluster_factor * rc[c] : ext * 2.0;
         int L = 4;
         double q = cap / (double)(1 << L);
         // quanta needed to cover the box must fit in maxbits per axis
@@ -570,6 +582,7 @@ struct Plan {
     int4 *qmap = nullptr;   // per query: (t, cluster size, pieces, first slot)
     int4 *pieces = nullptr;
     int *porder = nullptr;
+    PieceRec *recs = nullptr;
     int2 *cpieces = nullptr;
     int npieces = 0;
     long long nslots = 0;
@@ -623,6 +636,8 @@ Plan make_plan(cvo_context *ctx, const std::string &pre, const ClusterView &q, c
     bool in_tmp = false;
     launch_radix_sort(key, val, ktmp, vtmp, hist, bsum2, P, 32, ctx->stream, &in_tmp);
     pl.porder = in_tmp ? vtmp : val;
+    pl.recs = ctx->get_t<PieceRec>(pre + ".recs", std::max(P, 1));
+    launch_plan_records(pl.porder, pl.pieces, q.cpair, q.clus, q.cgeo, P, pl.recs, ctx->stream);
     ctx->check_launch("plan emit");
     int nslots = 0;
     ctx->download(&nslots, d_total + 1, sizeof(int));
@@ -682,6 +697,7 @@ PairPassArgs pass_args(const ClusterView &q, const GridView &r, const PairState 
     a.oL = m.L;
     a.pieces = pl.pieces;
     a.porder = pl.porder;
+    a.recs = pl.recs;
     a.npieces = pl.npieces;
     return a;
 }

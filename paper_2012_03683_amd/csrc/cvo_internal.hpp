@@ -52,10 +52,10 @@ struct alignas(16) PairState {
 };
 
 // Density class of an evaluation from its in-cutoff pairs per query point
-// (-1: unknown).  Dense classes get larger clusters and finer cells.
+// (-1: unknown): 3 from 2000, 2 from 500, 1 from 100, else 0.
 __host__ __device__ inline int density_class(double ppq)
 {
-    return !(ppq >= 0.0) ? -1 : (ppq >= 2000.0 ? 2 : (ppq >= 500.0 ? 1 : 0));
+    return !(ppq >= 0.0) ? -1 : (ppq >= 2000.0 ? 3 : (ppq >= 500.0 ? 2 : (ppq >= 100.0 ? 1 : 0)));
 }
 
 // Per-pair constants of the ascent.
@@ -104,6 +104,15 @@ struct FeatLayout {
 // range [c0, c1) of one cluster's candidate list (the concatenation of its
 // neighbourhood rows), planned so that heavy clusters are split.  One wave
 // per piece, pieces ordered heaviest first.
+// One piece in dispatch order with what its wave needs first, gathered at
+// planning time so the wave's prologue is one load: the piece (cluster, c0,
+// c1, first output slot), its pair, its cluster's points and geometry.
+struct alignas(32) PieceRec {
+    int4 pc;
+    int b, first, n, pad;
+    double4 geo;
+};
+
 struct PairPassArgs {
     // query side (cluster view)
     const float4 *qpts;
@@ -114,6 +123,7 @@ struct PairPassArgs {
     int nclus;
     const int4 *pieces;   // (cluster, c0, c1, first output slot), cluster-major
     const int *porder;    // processing order of the pieces: heaviest first
+    const PieceRec *recs; // the pieces in processing order, with their cluster data
     int npieces;
     // reference side (grid view)
     const float4 *rpts;

@@ -48,6 +48,9 @@ void launch_plan_emit(const PairPassArgs &a, const int *npieces, const int *pbas
 void launch_plan_slots(int4 *pieces, const int *tbase, int npieces, hipStream_t s);
 void launch_plan_qmap(const int2 *clus, const int2 *cpieces, const int4 *pieces, int nclus, int4 *qmap,
                       hipStream_t s);
+// recs[i] = piece porder[i] with its pair and cluster data (dispatch order)
+void launch_plan_records(const int *porder, const int4 *pieces, const int *cpair, const int2 *clus,
+                         const double4 *cgeo, int npieces, PieceRec *recs, hipStream_t s);
 
 
 // Where a query's partial moments live: qmap[j] = (t, n, np, s0) for query j

@@ -121,7 +121,7 @@ template <int SED, int LIND, int MODE> struct PassTraits {
     static constexpr int D = SED + LIND;
     static constexpr int D4 = (D + 3) & ~3;
     // waves per SIMD the register budget is sized for (no spills)
-    static constexpr int kMinWaves = (MODE == 0 && D4 <= 24) ? 3 : 2;
+    static constexpr int kMinWaves = (MODE == 0 && D4 <= 24) ? 4 : 2;
 };
 
 template <int SED, int LIND, int MODE>
@@ -150,9 +150,9 @@ void pair_pass_kernel(const PairPassArgs a)
     {
         const int tk = wave_uniform(blockIdx.x * kWavesPerBlock + wv);
         if (tk >= a.npieces) return;
-        const int4 pc = a.pieces[a.porder[tk]];
-        const int c = pc.x;
-        const int b = wave_uniform(a.cpair[c]);
+        const PieceRec rec = a.recs[tk];
+        const int4 pc = rec.pc;
+        const int b = wave_uniform(rec.b);
         const PairState *st = a.state + b;
         if (st->done || st->pause) return;
 
@@ -165,8 +165,8 @@ void pair_pass_kernel(const PairPassArgs a)
         const double sc = uniform_d(sqrt(ascale));
         const double rc = a.kappa * ell;
         const double rc2 = rc * rc;
-        const int2 cl = a.clus[c];
-        const double4 g = a.cgeo[c];
+        const int2 cl = make_int2(rec.first, rec.n);
+        const double4 g = rec.geo;
         const GridDesc gd = a.grids[b];
         const Neighbourhood nb = neighbourhood(Pm, g, rc, cut, gd);
         const double cx = uniform_d(nb.cx), cy = uniform_d(nb.cy), cz = uniform_d(nb.cz);
@@ -487,6 +487,31 @@ void launch_plan_qmap(const int2 *clus, const int2 *cpieces, const int4 *pieces,
 {
     const int nb = std::max(1, std::min(4096, (nclus + 255) / 256));
     hipLaunchKernelGGL(plan_qmap, dim3(nb), dim3(256), 0, s, clus, cpieces, pieces, nclus, qmap);
+}
+
+__global__ void plan_records(const int *porder, const int4 *pieces, const int *cpair, const int2 *clus,
+                             const double4 *cgeo, int npieces, PieceRec *recs)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npieces; i += gridDim.x * blockDim.x) {
+        const int4 pc = pieces[porder[i]];
+        const int2 cl = clus[pc.x];
+        PieceRec r;
+        r.pc = pc;
+        r.b = cpair[pc.x];
+        r.first = cl.x;
+        r.n = cl.y;
+        r.pad = 0;
+        r.geo = cgeo[pc.x];
+        recs[i] = r;
+    }
+}
+
+void launch_plan_records(const int *porder, const int4 *pieces, const int *cpair, const int2 *clus,
+                         const double4 *cgeo, int npieces, PieceRec *recs, hipStream_t s)
+{
+    if (npieces <= 0) return;
+    const int nb = std::max(1, std::min(4096, (npieces + 255) / 256));
+    hipLaunchKernelGGL(plan_records, dim3(nb), dim3(256), 0, s, porder, pieces, cpair, clus, cgeo, npieces, recs);
 }
 
 void launch_plan_count(const PairPassArgs &a, int work, int *npieces, int *cmax, long long *ccount, hipStream_t s)
