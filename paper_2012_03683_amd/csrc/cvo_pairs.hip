@@ -410,7 +410,7 @@ void pair_pass_kernel(const PairPassArgs a)
 // ---------------------------------------------------------------- planning
 // Per cluster, at the current pose: the number of candidates of its
 // neighbourhood and how many pieces to cut it into (work per piece about
-// `work` query-candidate products, at least 256 candidates per piece).
+// `work` query-candidate products, at least 512 candidates per piece).
 __global__ void plan_count(const PairPassArgs a, int work, int *npieces, int *cmax, long long *ccount)
 {
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < a.nclus; c += gridDim.x * blockDim.x) {
@@ -434,7 +434,7 @@ __global__ void plan_count(const PairPassArgs a, int work, int *npieces, int *cm
                 }
         }
         const int n = a.clus[c].y;
-        const int cm = max(256, work / max(n, 1));
+        const int cm = max(512, work / max(n, 1));
         const long long np = C > 0 ? (C + cm - 1) / cm : 1;
         npieces[c] = (int)min(np, 4096LL);
         cmax[c] = cm;
