@@ -575,9 +575,10 @@ ClusterView build_clusters(cvo_context *ctx, const std::string &pre, const std::
 }
 
 // ------------------------------------------------------------------ work plan
-// Pieces: every cluster's candidate list is cut into ranges of about
-// `piece_work` query x candidate products (planned at the pose in the device
-// state), and the pieces are processed heaviest first.
+// Pieces: every cluster's candidate list (at the pose in the device state) is
+// shared by pieces of about `piece_work` query x candidate products, each
+// taking every np-th chunk of 64 candidates, and the pieces are processed
+// heaviest first.
 struct Plan {
     int4 *qmap = nullptr;   // per query: (t, cluster size, pieces, first slot)
     int4 *pieces = nullptr;
@@ -628,7 +629,7 @@ Plan make_plan(cvo_context *ctx, const std::string &pre, const ClusterView &q, c
     int *hist = ctx->get_t<int>(pre + ".phist", ntiles * 256);
     int *bsum2 = ctx->get_t<int>(pre + ".pbsum2", (std::max<long long>(ntiles * 256, P) + 2047) / 2048 + 1);
     pl.cpieces = ctx->get_t<int2>(pre + ".cpieces", nc);
-    launch_plan_emit(a, npc, pbase, cmax, ccount, pl.pieces, pn, key, val, pl.cpieces, ctx->stream);
+    launch_plan_emit(a, npc, pbase, ccount, pl.pieces, pn, key, val, pl.cpieces, ctx->stream);
     launch_exclusive_scan(pn, tbase, bsum2, P, d_total + 1, ctx->stream);
     launch_plan_slots(pl.pieces, tbase, P, ctx->stream);
     pl.qmap = ctx->get_t<int4>(pre + ".qmap", std::max<long long>(q.ntot, 1));

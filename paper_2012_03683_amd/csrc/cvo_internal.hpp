@@ -100,13 +100,13 @@ struct FeatLayout {
     float sig2;        // sigma^2 * prod_b sigma_b^2 over SE blocks
 };
 
-// Arguments of the pair pass.  The unit of work is a piece: a contiguous
-// range [c0, c1) of one cluster's candidate list (the concatenation of its
-// neighbourhood rows), planned so that heavy clusters are split.  One wave
-// per piece, pieces ordered heaviest first.
+// Arguments of the pair pass.  The unit of work is a piece: piece p of np
+// takes every np-th 64-candidate chunk of one cluster's candidate list (the
+// concatenation of its neighbourhood rows), so heavy clusters are split into
+// pieces of similar work.  One wave per piece, pieces ordered heaviest first.
 // One piece in dispatch order with what its wave needs first, gathered at
-// planning time so the wave's prologue is one load: the piece (cluster, c0,
-// c1, first output slot), its pair, its cluster's points and geometry.
+// planning time so the wave's prologue is one load: the piece (cluster, p,
+// np, first output slot), its pair, its cluster's points and geometry.
 struct alignas(32) PieceRec {
     int4 pc;
     int b, first, n, pad;
@@ -121,7 +121,7 @@ struct PairPassArgs {
     const double4 *cgeo;  // (centre xyz in the query frame, radius)
     const int *cpair;     // pair of each cluster
     int nclus;
-    const int4 *pieces;   // (cluster, c0, c1, first output slot), cluster-major
+    const int4 *pieces;   // (cluster, piece index p, pieces np, first output slot), cluster-major
     const int *porder;    // processing order of the pieces: heaviest first
     const PieceRec *recs; // the pieces in processing order, with their cluster data
     int npieces;

@@ -42,9 +42,8 @@ void launch_cluster_emit(const int *head, const int *hidx, const int2 *span, con
 // returns false when no kernel exists for the feature layout
 bool launch_pair_pass(const PairPassArgs &a, const FeatLayout &lay, int mode, hipStream_t s);
 void launch_plan_count(const PairPassArgs &a, int work, int *npieces, int *cmax, long long *ccount, hipStream_t s);
-void launch_plan_emit(const PairPassArgs &a, const int *npieces, const int *pbase, const int *cmax,
-                      const long long *ccount, int4 *pieces, int *pn, unsigned long long *key, int *val,
-                      int2 *cpieces, hipStream_t s);
+void launch_plan_emit(const PairPassArgs &a, const int *npieces, const int *pbase, const long long *ccount,
+                      int4 *pieces, int *pn, unsigned long long *key, int *val, int2 *cpieces, hipStream_t s);
 void launch_plan_slots(int4 *pieces, const int *tbase, int npieces, hipStream_t s);
 void launch_plan_qmap(const int2 *clus, const int2 *cpieces, const int4 *pieces, int nclus, int4 *qmap,
                       hipStream_t s);

@@ -294,15 +294,18 @@ void pair_pass_kernel(const PairPassArgs a)
             Dz += (double)dz32;
         };
 
-        // this piece covers candidates [c0, c1) of the concatenated rows
-        const int c0 = pc.y, c1 = pc.z;
+        // this piece takes chunks pidx, pidx + np, pidx + 2 np, ... of the
+        // cluster's candidates (the neighbourhood rows concatenated; chunk k =
+        // candidates [64 k, 64 k + 64)), so the np pieces of a cluster sample
+        // its whole neighbourhood alike and together cover it at any pose
+        const int pidx = pc.y, pstride = pc.z;
         int qn = 0;
         if (nb.any) {
             const int nyr = nb.iy1 - nb.iy0 + 1;
             const int nrows = nyr * (nb.iz1 - nb.iz0 + 1);
             const int run = nb.ix1 - nb.ix0 + 1;
             int base = 0;  // candidates in earlier row batches
-            for (int rb = 0; rb < nrows && base < c1; rb += kWave) {
+            for (int rb = 0; rb < nrows; rb += kWave) {
                 const int r = rb + lane;
                 int rs = 0, len = 0;
                 if (r < nrows) {
@@ -319,18 +322,20 @@ void pair_pass_kernel(const PairPassArgs a)
                     if (lane >= off) incl += v;
                 }
                 const int total = __shfl(incl, kWave - 1);
-                const int m_lo = max(c0 - base, 0);
-                const int m_hi = min(c1 - base, total);
-                if (m_lo < m_hi) {
+                // first chunk of this piece reaching into [base, base + total)
+                int k = base / kWave;
+                k += ((pidx - k) % pstride + pstride) % pstride;
+                if (k * kWave < base + total) {
                     s_rs[wv][lane] = rs;
                     s_rx[wv][lane] = incl - len;
                     wave_sync();
-                    for (int m0 = m_lo; m0 < m_hi; m0 += kWave) {
-                        const int m = m0 + lane;
+                    for (; k * kWave < base + total; k += pstride) {
+                        // the part of chunk k inside this batch of rows
+                        const int m = k * kWave - base + lane;
                         bool keep = false;
                         int src = 0;
                         float x0 = 0.f, x1 = 0.f, x2 = 0.f;
-                        if (m < m_hi) {
+                        if (m >= 0 && m < total) {
                             int lo_ = 0, hi_ = kWave - 1;
                             while (lo_ < hi_) {
                                 const int mid = (lo_ + hi_ + 1) >> 1;
@@ -442,23 +447,21 @@ __global__ void plan_count(const PairPassArgs a, int work, int *npieces, int *cm
     }
 }
 
-// Emit the pieces of each cluster (cluster-major), their query counts (for
-// the output-slot scan) and a sort key: the heaviest piece gets the smallest key.
-__global__ void plan_emit(const PairPassArgs a, const int *npieces, const int *pbase, const int *cmax,
-                          const long long *ccount, int4 *pieces, int *pn, unsigned long long *key, int *val,
-                          int2 *cpieces)
+// Emit the pieces of each cluster (cluster-major) as (cluster, p, np), their
+// query counts (for the output-slot scan) and a sort key: the heaviest piece
+// gets the smallest key; the stable sort keeps a cluster's pieces together.
+__global__ void plan_emit(const PairPassArgs a, const int *npieces, const int *pbase, const long long *ccount,
+                          int4 *pieces, int *pn, unsigned long long *key, int *val, int2 *cpieces)
 {
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < a.nclus; c += gridDim.x * blockDim.x) {
-        const int np = npieces[c], pb = pbase[c], cm = cmax[c];
+        const int np = npieces[c], pb = pbase[c];
         const int n = a.clus[c].y;
         const long long C = ccount[c];
         cpieces[c] = make_int2(pb, np);
+        const long long cand = (C + np - 1) / np;  // candidates per piece
         for (int p = 0; p < np; ++p) {
-            const int c0 = p * cm;
-            const int c1 = (p == np - 1) ? 0x7fffffff : (p + 1) * cm;
-            pieces[pb + p] = make_int4(c, c0, c1, 0);
+            pieces[pb + p] = make_int4(c, p, np, 0);
             pn[pb + p] = n;
-            const long long cand = (p == np - 1) ? max(C - (long long)c0, 0LL) : (long long)cm;
             const unsigned long long cost = (unsigned long long)n * (unsigned long long)(cand + 64);
             key[pb + p] = 0xffffffffULL - (cost > 0xffffffffULL ? 0xffffffffULL : cost);
             val[pb + p] = pb + p;
@@ -520,12 +523,11 @@ void launch_plan_count(const PairPassArgs &a, int work, int *npieces, int *cmax,
     hipLaunchKernelGGL(plan_count, dim3(nb), dim3(256), 0, s, a, work, npieces, cmax, ccount);
 }
 
-void launch_plan_emit(const PairPassArgs &a, const int *npieces, const int *pbase, const int *cmax,
-                      const long long *ccount, int4 *pieces, int *pn, unsigned long long *key, int *val,
-                      int2 *cpieces, hipStream_t s)
+void launch_plan_emit(const PairPassArgs &a, const int *npieces, const int *pbase, const long long *ccount,
+                      int4 *pieces, int *pn, unsigned long long *key, int *val, int2 *cpieces, hipStream_t s)
 {
     const int nb = std::max(1, std::min(4096, (a.nclus + 255) / 256));
-    hipLaunchKernelGGL(plan_emit, dim3(nb), dim3(256), 0, s, a, npieces, pbase, cmax, ccount, pieces, pn, key, val,
+    hipLaunchKernelGGL(plan_emit, dim3(nb), dim3(256), 0, s, a, npieces, pbase, ccount, pieces, pn, key, val,
                        cpieces);
 }
 
