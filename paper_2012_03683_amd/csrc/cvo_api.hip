@@ -60,7 +60,7 @@ struct cvo_context {
     std::map<std::string, Buf> bufs;
     void *pinned = nullptr;
     size_t pinned_cap = 0;
-    cvo_tuning tuning{16, 1.0, 0.5, 0.6, 16, 8192, 1};
+    cvo_tuning tuning{16, 1.0, 0.5, 0.6, 16, 512, 1};
     bool profiling = false;
     cvo_timing timing{0, 0.0, 0, 0};
     std::vector<hipEvent_t> ev_free;
