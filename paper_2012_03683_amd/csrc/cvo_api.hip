@@ -456,7 +456,7 @@ GridView build_grid(cvo_context *ctx, const std::string &pre, const std::vector<
     unsigned long long *ktmp = ctx->get_t<unsigned long long>(pre + ".ktmp", ntot);
     int *vals = ctx->get_t<int>(pre + ".vals", ntot);
     int *vtmp = ctx->get_t<int>(pre + ".vtmp", ntot);
-    const long long ntiles = (ntot + 4095) / 4096;
+    const long long ntiles = (ntot + kRadixTile - 1) / kRadixTile;
     int *hist = ctx->get_t<int>(pre + ".hist", ntiles * 256);
     int *bsum = ctx->get_t<int>(pre + ".bsum", (ntiles * 256 + 2047) / 2048 + 1);
     v.pts = ctx->get_t<float4>(pre + ".pts", ntot);
@@ -491,6 +491,7 @@ ClusterView build_clusters(cvo_context *ctx, const std::string &pre, const std::
     std::vector<long long> bases(B);
     v.desc.resize(B);
     long long pt_base = 0, nmax = 0;
+    int bits = 1;  // Morton bits per axis: as many as the widest cloud needs
     for (int c = 0; c < B; ++c) {
         const long long n = cl[c].n;
         ClusterBuild &g = cb[c];
@@ -509,6 +510,8 @@ ClusterView build_clusters(cvo_context *ctx, const std::string &pre, const std::
             L = std::max(0, (int)std::floor(std::log2(std::max(cap / q, 1.0))));
         }
         L = std::min(L, maxbits);
+        // quanta along the widest axis (+1 for rounding at the far face)
+        bits = std::max({bits, L, bits_for((unsigned long long)std::floor(ext / q) + 1)});
         g.ox = lo[0];
         g.oy = lo[1];
         g.oz = lo[2];
@@ -526,7 +529,7 @@ ClusterView build_clusters(cvo_context *ctx, const std::string &pre, const std::
         nmax = std::max(nmax, n);
     }
     v.ntot = pt_base;
-    const int bits = maxbits;
+    bits = std::min(bits, maxbits);
     ClusterBuild *d_cb = ctx->get_t<ClusterBuild>(pre + ".cb", B);
     ctx->upload(d_cb, cb.data(), sizeof(ClusterBuild) * B);
     long long *d_base = ctx->get_t<long long>(pre + ".base", B);
@@ -540,7 +543,7 @@ ClusterView build_clusters(cvo_context *ctx, const std::string &pre, const std::
     unsigned long long *ktmp = ctx->get_t<unsigned long long>(pre + ".ktmp", ntot);
     int *vals = ctx->get_t<int>(pre + ".vals", ntot);
     int *vtmp = ctx->get_t<int>(pre + ".vtmp", ntot);
-    const long long ntiles = (ntot + 4095) / 4096;
+    const long long ntiles = (ntot + kRadixTile - 1) / kRadixTile;
     int *hist = ctx->get_t<int>(pre + ".hist", std::max(ntiles * 256, ntot));
     int *bsum = ctx->get_t<int>(pre + ".bsum", (std::max(ntiles * 256, ntot) + 2047) / 2048 + 1);
     v.pts = ctx->get_t<float4>(pre + ".pts", ntot);
@@ -625,7 +628,7 @@ Plan make_plan(cvo_context *ctx, const std::string &pre, const ClusterView &q, c
     unsigned long long *ktmp = ctx->get_t<unsigned long long>(pre + ".pktmp", P);
     int *val = ctx->get_t<int>(pre + ".pval", P);
     int *vtmp = ctx->get_t<int>(pre + ".pvtmp", P);
-    const long long ntiles = (P + 4095) / 4096;
+    const long long ntiles = (P + kRadixTile - 1) / kRadixTile;
     int *hist = ctx->get_t<int>(pre + ".phist", ntiles * 256);
     int *bsum2 = ctx->get_t<int>(pre + ".pbsum2", (std::max<long long>(ntiles * 256, P) + 2047) / 2048 + 1);
     pl.cpieces = ctx->get_t<int2>(pre + ".cpieces", nc);
@@ -635,7 +638,7 @@ Plan make_plan(cvo_context *ctx, const std::string &pre, const ClusterView &q, c
     pl.qmap = ctx->get_t<int4>(pre + ".qmap", std::max<long long>(q.ntot, 1));
     launch_plan_qmap(q.clus, pl.cpieces, pl.pieces, nc, pl.qmap, ctx->stream);
     bool in_tmp = false;
-    launch_radix_sort(key, val, ktmp, vtmp, hist, bsum2, P, 32, ctx->stream, &in_tmp);
+    launch_radix_sort(key, val, ktmp, vtmp, hist, bsum2, P, 24, ctx->stream, &in_tmp);
     pl.porder = in_tmp ? vtmp : val;
     pl.recs = ctx->get_t<PieceRec>(pre + ".recs", std::max(P, 1));
     launch_plan_records(pl.porder, pl.pieces, q.cpair, q.clus, q.cgeo, P, pl.recs, ctx->stream);

@@ -205,8 +205,8 @@ void launch_exclusive_scan(const int *in, int *out, int *bsum, long long n, int 
 
 // ---------------------------------------------------------------- radix sort
 constexpr int kRadixThreads = 256;
-constexpr int kRadixItems = 16;
-constexpr int kRadixTile = kRadixThreads * kRadixItems;
+constexpr int kRadixItems = kRadixTile / kRadixThreads;
+static_assert(kRadixTile % kRadixThreads == 0, "radix tile");
 
 __global__ __launch_bounds__(kRadixThreads) void radix_hist(const unsigned long long *keys, long long n,
                                                             int shift, int *hist, int ntiles)

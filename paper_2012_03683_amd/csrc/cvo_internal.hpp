@@ -28,6 +28,7 @@ constexpr int kWavesPerBlock = 1;  // pair pass: one wave per workgroup, so a fi
 constexpr int kQueueCap = 80;    // LDS candidate queue per wave
 constexpr int kQueueFlush = 16;  // process the queue once it holds this many (cap >= flush + 64)
 constexpr int kTraceLen = 8;
+constexpr int kRadixTile = 1024;  // keys per workgroup and pass of the radix sort
 constexpr int kRedVals = 40;     // values reduced per pair by the reduction kernel
 constexpr int kRedThreads = 256;
 

@@ -463,7 +463,7 @@ __global__ void plan_emit(const PairPassArgs a, const int *npieces, const int *p
             pieces[pb + p] = make_int4(c, p, np, 0);
             pn[pb + p] = n;
             const unsigned long long cost = (unsigned long long)n * (unsigned long long)(cand + 64);
-            key[pb + p] = 0xffffffffULL - (cost > 0xffffffffULL ? 0xffffffffULL : cost);
+            key[pb + p] = 0xffffffULL - (cost > 0xffffffULL ? 0xffffffULL : cost);  // 24-bit key
             val[pb + p] = pb + p;
         }
     }
