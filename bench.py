@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--batched", type=int, default=16,
+                    help="pairs in the batched-vs-plain comparison of the extras (64 = the full batched workload)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -185,6 +187,7 @@ def main():
             "traffic": measured_traffic(),
             "kernel": "pair_pass_kernel<5,19,0>",
             "ops_per_pair": opp,
+            "kernel_pair_evals_per_s": (tim["pair_count"] + metric_pairs) / kernel_s if kernel_s > 0 else 0.0,
             "avg_launch_ms": tim["pair_ms"] / max(tim["pair_launches"], 1),
             "launches": tim["pair_launches"],
         },
@@ -193,7 +196,7 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, rep_last)
     if not args.no_extra:
-        out["extra"] = extras(cvo, torch, synth, dev)
+        out["extra"] = extras(cvo, torch, synth, dev, args.batched)
     print(json.dumps(out))
 
 
@@ -218,6 +221,7 @@ def cpu_baseline(p, rep):
         "value": pairs / sec,
         "unit": "pair-evals/s",
         "cores": oracle.num_threads(),
+        "candidates_per_s": len(ells) * p.x.shape[0] * p.z.shape[0] / sec,
         "kind": "oracle",
         "sample": f"{len(ells)} FP64 oracle evaluations (F, gradient, curvature; brute force over all "
                   f"{p.x.shape[0] * p.z.shape[0]:.1e} candidate pairs each) of the same stereo pair at the anneal's "
@@ -226,44 +230,49 @@ def cpu_baseline(p, rep):
     }
 
 
-def extras(cvo, torch, synth, dev):
+def extras(cvo, torch, synth, dev, nbatch):
+    """Figures for the other workloads (each timed after one untimed run)."""
     ex = {}
-    # batched form (64 mixed pairs) vs looping the plain path
-    pairs = synth.batched_pairs(seed=1004, batch=16)
-    tens = []
-    for q in pairs:
-        tens.append((torch.from_numpy(q.x).to(dev), torch.from_numpy(q.z).to(dev),
-                     torch.from_numpy(q.u).to(dev), torch.from_numpy(q.v).to(dev)))
-    prm = [q.align for q in pairs]
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, r
+
+    # RGB-D indoor: 40k + 40k points, 5 SE, ell 0.1 -> 0.05, then the metric
+    q = synth.rgbd_pair(seed=1002)
+    X, Z, U, V = (torch.from_numpy(a).to(dev) for a in (q.x, q.z, q.u, q.v))
+    sec, (T, rep, _) = timed(lambda: cvo.cvo_align(X, Z, U, V, q.spec, q.align), 3)
+    ex["rgbd_registration_ms"] = 1e3 * sec
+    ex["rgbd_pair_evals_per_s"] = rep["total_pairs"] / sec
+    ex["rgbd_iterations"] = int(rep["iterations"])
+    # tiny cube: 2k + 2k points, 50 fixed ascent iterations at ell = 0.1
+    q = synth.tiny_cube(seed=1000)
+    X, Z, U, V = (torch.from_numpy(a).to(dev) for a in (q.x, q.z, q.u, q.v))
+    sec, _ = timed(lambda: cvo.cvo_align(X, Z, U, V, q.spec, q.align), 5)
+    ex["tiny_cube_50_iterations_ms"] = 1e3 * sec
+    # batched form vs looping the plain path
+    pairs = synth.batched_pairs(seed=1004, batch=nbatch)
+    tens = [tuple(torch.from_numpy(a).to(dev) for a in (b.x, b.z, b.u, b.v)) for b in pairs]
+    prm = [b.align for b in pairs]
     spec = pairs[0].spec
-    torch.cuda.synchronize()
-    cvo.cvo_align_batched(tens, spec, prm)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    Tb, rb = cvo.cvo_align_batched(tens, spec, prm)
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    for (X, Z, U, V), pr in zip(tens, prm):
-        cvo.cvo_align(X, Z, U, V, spec, pr)
-    torch.cuda.synchronize()
-    tp = time.perf_counter() - t0
+    tb, _ = timed(lambda: cvo.cvo_align_batched(tens, spec, prm), 1)
+    tp, _ = timed(lambda: [cvo.cvo_align(X, Z, U, V, spec, pr) for (X, Z, U, V), pr in zip(tens, prm)], 1)
     ex["batched_pairs"] = len(pairs)
     ex["batched_registrations_per_s"] = len(pairs) / tb
     ex["plain_loop_registrations_per_s"] = len(pairs) / tp
-    # backward form: 8 stereo pairs of 10k points, 32-dim LIN features
+    # backward form: stereo-shaped pairs of 10k points, 32-dim LIN features
     lb = synth.learned_batch(seed=1003, batch=2)
     tot = 0.0
     for q in lb:
-        X = torch.from_numpy(q.x).to(dev); Z = torch.from_numpy(q.z).to(dev)
-        U = torch.from_numpy(q.u).to(dev); V = torch.from_numpy(q.v).to(dev)
-        cvo.cvo_inner_product_backward(X, Z, q.T_eval, q.ell, 1.0, U, V, q.spec)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        cvo.cvo_inner_product(X, Z, q.T_eval, q.ell, U, V, q.spec)
-        cvo.cvo_inner_product_backward(X, Z, q.T_eval, q.ell, 1.0, U, V, q.spec)
-        torch.cuda.synchronize()
-        tot += time.perf_counter() - t0
+        X, Z, U, V = (torch.from_numpy(a).to(dev) for a in (q.x, q.z, q.u, q.v))
+        sec, _ = timed(lambda: (cvo.cvo_inner_product(X, Z, q.T_eval, q.ell, U, V, q.spec),
+                                cvo.cvo_inner_product_backward(X, Z, q.T_eval, q.ell, 1.0, U, V, q.spec)), 3)
+        tot += sec
     ex["forward_backward_ms_per_pair_10k_lin32"] = 1e3 * tot / len(lb)
     return ex
 
