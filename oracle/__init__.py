@@ -159,6 +159,19 @@ def evaluate(x, u, z, v, spec, ell, T=None, sigma=1.0, kappa=3.0, direction=None
             "i_theta": out[17], "n_pairs": int(n.value)}
 
 
+def cosine(x, u, z, v, spec, ell, T=None, sigma=1.0, kappa=3.0):
+    """Cosine of the angle between f_X and the moved f_Z (eq. (9), Sec. III-C):
+    <f_X, h.f_Z> / (||f_X|| ||f_Z||), the squared norms being the self inner
+    products F(X, X; I) and F(Z, Z; I) with the same kernels and cutoff.
+    Returns (cos_theta, F_XZ, F_XX, F_ZZ); cos_theta is 0 when a squared norm
+    is not positive."""
+    fxz = evaluate(x, u, z, v, spec, ell, T, sigma, kappa)["F"]
+    fxx = evaluate(x, u, x, u, spec, ell, None, sigma, kappa)["F"]
+    fzz = evaluate(z, v, z, v, spec, ell, None, sigma, kappa)["F"]
+    c = fxz / (np.sqrt(fxx) * np.sqrt(fzz)) if fxx > 0 and fzz > 0 else 0.0
+    return c, fxz, fxx, fzz
+
+
 def target_moments(x, u, z, v, spec, ell, idx, T=None, sigma=1.0, kappa=3.0):
     """Per-target W_j, D_j, S_j (upper triangle), n_j for targets j in idx."""
     p = _Pair(x, u, z, v, spec)

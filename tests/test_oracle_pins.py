@@ -315,6 +315,67 @@ def test_indicator_peaks_at_zero_misalignment():
     assert np.all(np.diff(tv) < 0)
 
 
+# ------------------------------------------------------------ cosine of the angle (eq. (9))
+def test_cosine_equals_indicator_when_kernel_is_a_delta():
+    """Remark and corollary of Sec. III-C: with points farther apart than the
+    cutoff (k(x_i, x_j) = delta_ij) and c_ii = 1 the squared norms are |X| and
+    |Z|, so cos(theta) of eq. (9) equals i_theta of eq. (10)."""
+    ax = np.arange(3, dtype=np.float64)
+    x = np.stack(np.meshgrid(ax, ax, ax, indexing="ij"), -1).reshape(-1, 3)
+    z = x + np.array([0.05, -0.03, 0.02])
+    rng = np.random.default_rng(5)
+    u = rng.uniform(0, 1, (27, 5))
+    v = rng.uniform(0, 1, (27, 5))
+    spec = [synth.se_block(5, 0.4)]
+    c, fxz, fxx, fzz = oracle.cosine(x, u, z, v, spec, 0.1)
+    assert fxx == 27.0 and fzz == 27.0
+    r = oracle.evaluate(x, u, z, v, spec, 0.1)
+    assert r["n_pairs"] == 27 and fxz == r["F"]
+    assert c == pytest.approx(r["i_theta"], rel=1e-15)
+
+
+def test_cosine_is_one_at_exact_alignment():
+    """cos(theta) = 1 for identical clouds at the identity (bit for bit), and
+    within float32 storage of the coordinates when the pose undoes a rigid
+    motion of the cloud (rigid invariance of both norms)."""
+    p = synth.tiny_cube(seed=31, n=500)
+    c, fxz, fxx, fzz = oracle.cosine(p.x, p.u, p.x, p.u, p.spec, 0.1)
+    assert c == 1.0 and fxz == fxx == fzz
+    R = Rotation.from_rotvec([0.3, -0.2, 0.5]).as_matrix()
+    T = _pose(R, [0.4, -0.1, 0.2])
+    zm = ((p.x - T[:3, 3]) @ R).astype(np.float32)  # z = T^-1 x
+    c2, fxz2, fxx2, fzz2 = oracle.cosine(p.x, p.u, zm, p.u, p.spec, 0.1, T=T)
+    assert c2 == pytest.approx(1.0, abs=1e-5)
+    assert fzz2 == pytest.approx(fxx2, rel=1e-5)
+
+
+def test_cosine_obeys_cauchy_schwarz_without_cutoff():
+    """With no cutoff the squared-exponential kernels are positive definite,
+    so |cos(theta)| <= 1 for any clouds and pose, with equality only at the
+    alignment."""
+    spec = [synth.se_block(3, 0.6)]
+    rng = np.random.default_rng(11)
+    for seed in range(4):
+        q = _small(seed=seed, n=30, m=25, spec=spec, extent=0.5)
+        x, u, z, v = q.x, q.u, q.z, q.v
+        xi = rng.normal(0, 0.2, 6)
+        c, fxz, fxx, fzz = oracle.cosine(x, u, z, v, spec, 0.3, T=oracle.exp_se3(xi), kappa=INF)
+        assert 0.0 < c < 1.0
+        assert fxz * fxz <= fxx * fzz
+
+
+def test_cosine_peaks_at_zero_misalignment():
+    """Fig. 3 of Sec. III-C with the exact cosine: rotating or translating a
+    cloud against itself lowers cos(theta) from 1."""
+    p = synth.tiny_cube(seed=78, n=600)
+    axis = np.array([0.6, -0.3, 0.74]) / np.linalg.norm([0.6, -0.3, 0.74])
+    vals = [oracle.cosine(p.x, p.u, p.x, p.u, p.spec, 0.1, T=oracle.exp_se3(np.r_[th * axis, 0, 0, 0]))[0]
+            for th in np.deg2rad([0, 0.5, 1, 2, 4])]
+    assert vals[0] == 1.0 and np.all(np.diff(vals) < 0)
+    tv = [oracle.cosine(p.x, p.u, p.x, p.u, p.spec, 0.1, T=_pose(t=d * axis))[0] for d in [0.0, 0.01, 0.03, 0.1]]
+    assert tv[0] == 1.0 and np.all(np.diff(tv) < 0)
+
+
 # ------------------------------------------------------------ ascent (Problem 1) and annealing (Sec. IV)
 def test_noise_free_recovery():
     """Z = T_gt^-1 X exactly (up to float32 storage): T_gt is a stationary
