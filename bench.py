@@ -250,6 +250,10 @@ def extras(cvo, torch, synth, dev, nbatch):
     ex["rgbd_registration_ms"] = 1e3 * sec
     ex["rgbd_pair_evals_per_s"] = rep["total_pairs"] / sec
     ex["rgbd_iterations"] = int(rep["iterations"])
+    # exact cosine of eq. (9) on the RGB-D pair at its registered pose (three pair passes)
+    sec, cs = timed(lambda: cvo.cvo_cosine(X, Z, T, rep["final_ell"], U, V, q.spec), 5)
+    ex["rgbd_cosine_ms"] = 1e3 * sec
+    ex["rgbd_cosine_at_result"] = cs[0]
     # tiny cube: 2k + 2k points, 50 fixed ascent iterations at ell = 0.1
     q = synth.tiny_cube(seed=1000)
     X, Z, U, V = (torch.from_numpy(a).to(dev) for a in (q.x, q.z, q.u, q.v))

@@ -199,6 +199,17 @@ cvo_status cvo_evaluate(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,
                         const cvo_feature_spec *spec, const cvo_kernel_params *kp,
                         const double T[12], cvo_eval *out);
 
+/* Cosine of the angle between f_X and the moved f_Z (eq. (9), Sec. III-C):
+ * cos_theta = F(X, Z; T) / (||f_X|| ||f_Z||), where ||f_X||^2 = F(X, X; I) and
+ * ||f_Z||^2 = F(Z, Z; I) are the self inner products with the same kernels,
+ * lengthscale and cutoff.  Three pair passes on the handle's stream.
+ * sums, if non-NULL, receives {F(X,Z;T), F(X,X;I), F(Z,Z;I)} (host memory).
+ * cos_theta is 0 when a squared norm is not positive (an empty cloud).
+ * Errors as cvo_inner_product. */
+cvo_status cvo_cosine(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,
+                      const cvo_feature_spec *spec, const cvo_kernel_params *kp,
+                      const double T[12], double *cos_theta, double sums[3]);
+
 /* Alignment indicator i_theta = F / sqrt(|X||Z|) at (T, ell) (eq. (10),
  * Sec. III-C); 0 when either cloud is empty. */
 cvo_status cvo_metric(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,

@@ -30,7 +30,7 @@ CVO_TRACE_LEN = 8
 MAX_BLOCKS = 8
 
 EXPORTS = ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_last_error", "cvo_inner_product",
-           "cvo_gradient", "cvo_evaluate", "cvo_metric", "cvo_align", "cvo_inner_product_backward",
+           "cvo_gradient", "cvo_evaluate", "cvo_metric", "cvo_cosine", "cvo_align", "cvo_inner_product_backward",
            "cvo_align_batched", "cvo_get_tuning", "cvo_set_tuning", "cvo_autotune",
            "cvo_set_profiling", "cvo_get_timing")
 
@@ -108,6 +108,7 @@ def load_library(path: str = LIB_PATH):
     lib.cvo_gradient.argtypes = common + [P(C.c_double), C.c_void_p, P(C.c_int64)]
     lib.cvo_evaluate.argtypes = common + [P(cvo_eval)]
     lib.cvo_metric.argtypes = common + [P(C.c_double)]
+    lib.cvo_cosine.argtypes = common + [P(C.c_double), C.c_void_p]
     lib.cvo_align.argtypes = [H, P(cvo_cloud), P(cvo_cloud), P(cvo_feature_spec), P(cvo_align_params),
                               C.c_void_p, C.c_void_p, P(cvo_align_report), C.c_void_p]
     lib.cvo_inner_product_backward.argtypes = common + [C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -265,6 +266,21 @@ def cvo_evaluate(X, Z, T, ell, U=None, V=None, spec=None, sigma=1.0, kappa=3.0):
     del keep
     return {"F": out.F, "grad": np.array(out.grad[:]), "curv": out.curv, "dF_dell": out.dF_dell,
             "r_max": out.r_max, "i_theta": out.i_theta, "n_pairs": int(out.n_pairs)}
+
+
+def cvo_cosine(X, Z, T, ell, U=None, V=None, spec=None, sigma=1.0, kappa=3.0):
+    """Cosine of the angle between f_X and the moved f_Z (eq. (9)); returns
+    (cos_theta, F(X,Z;T), F(X,X;I), F(Z,Z;I))."""
+    h = handle()
+    cx, cz, keep, sp = _prep(X, Z, U, V, spec)
+    kp = cvo_kernel_params(ell, sigma, kappa)
+    Tp = _pose(T)
+    v = C.c_double()
+    sums = (C.c_double * 3)()
+    _check(load_library().cvo_cosine(h, C.byref(cx), C.byref(cz), C.byref(sp), C.byref(kp), Tp.ctypes.data,
+                                     C.byref(v), sums), h)
+    del keep
+    return v.value, sums[0], sums[1], sums[2]
 
 
 def cvo_metric(X, Z, T, ell, U=None, V=None, spec=None, sigma=1.0, kappa=3.0):

@@ -1170,6 +1170,27 @@ cvo_status cvo_metric(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z, cons
     });
 }
 
+cvo_status cvo_cosine(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z, const cvo_feature_spec *spec,
+                      const cvo_kernel_params *kp, const double T[12], double *cos_theta, double sums[3])
+{
+    return guarded(h, [&] {
+        require(cos_theta != nullptr, "output is NULL");
+        static const double I[12] = {1.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0};
+        PairState sxz, sxx, szz;
+        evaluate_one(h, X, Z, spec, kp, T, &sxz);
+        evaluate_one(h, X, X, spec, kp, I, &sxx);
+        evaluate_one(h, Z, Z, spec, kp, I, &szz);
+        const double fxz = (X->n > 0 && Z->n > 0) ? sxz.F : 0.0;
+        const double fxx = X->n > 0 ? sxx.F : 0.0, fzz = Z->n > 0 ? szz.F : 0.0;
+        *cos_theta = (fxx > 0.0 && fzz > 0.0) ? fxz / (std::sqrt(fxx) * std::sqrt(fzz)) : 0.0;
+        if (sums) {
+            sums[0] = fxz;
+            sums[1] = fxx;
+            sums[2] = fzz;
+        }
+    });
+}
+
 cvo_status cvo_align(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z, const cvo_feature_spec *spec,
                      const cvo_align_params *ap, const double T_init[12], double T_out[12],
                      cvo_align_report *report, double *trace)
