@@ -254,6 +254,21 @@ def align(x, u, z, v, spec, params=None, T_init=None, trace=True):
     return T, report, (tr[:it].copy() if trace else None)
 
 
+def odometry(frames, spec, first=None, rest=None):
+    """Frame-to-frame registration (Sec. IV): pair k registers frame k + 1 to
+    frame k; the first pair starts at the identity with `first`, every later
+    one at the previous pair's estimate with `rest`.  frames = [(xyz, feat)];
+    returns the relative poses (4x4, frame k + 1 into frame k) and reports."""
+    T = np.eye(4)
+    rel, reps = [], []
+    for k in range(len(frames) - 1):
+        (x, u), (z, v) = frames[k], frames[k + 1]
+        T, rep, _ = align(x, u, z, v, spec, first if k == 0 else rest, T_init=T, trace=False)
+        rel.append(T)
+        reps.append(rep)
+    return rel, reps
+
+
 def backward(x, u, z, v, spec, ell, T=None, sigma=1.0, kappa=3.0):
     """dF/dx, dF/dz, dF/du, dF/dv, dF/dell on the frozen pair set."""
     p = _Pair(x, u, z, v, spec)

@@ -245,6 +245,50 @@ def stereo_pair(seed=1001, n=30000, m=None, motion=None, semantic=True, ell_init
                 align=dict(ell_init=ell_init, ell_min=ell_min, max_iter=4000))
 
 
+@dataclass
+class Sequence:
+    """Frames of one camera moving through a scene: frame k is (xyz, features)
+    in camera k's frame; poses[k] maps camera k into the world (frame 0 = I)."""
+    name: str
+    frames: list
+    spec: list
+    poses: list
+    first: dict            # ascent parameters of the first pair (from identity)
+    rest: dict             # ascent parameters of later pairs (warm-started)
+
+    def relative(self, k):
+        """Ground-truth pose of frame k + 1 in frame k's coordinates."""
+        return _inv(self.poses[k]) @ self.poses[k + 1]
+
+
+def stereo_sequence(seed=1005, frames=8, n=30000, step=1.0, yaw_deg=2.0, semantic=True):
+    """Frame-to-frame sequence in the stereo-outdoor scene: the camera moves
+    `step` m (+-20%) along its optical axis per frame and turns `yaw_deg`
+    (+-30%) about its vertical axis; every frame samples its own pixels among
+    the hits of every second pixel row and column (depth noise 5e-4 d^2).  The
+    first pair starts at the identity with
+    ell 0.95 -> 0.1, later pairs at the previous estimate with ell 0.1."""
+    rng = np.random.default_rng(seed)
+    scene = _stereo_scene(rng)
+    freq, phase = _tex_params(rng, 3.0)
+    poses = [np.eye(4)]
+    for _ in range(frames - 1):
+        yaw = np.deg2rad(yaw_deg) * (1.0 + 0.3 * rng.uniform(-1.0, 1.0))
+        fwd = step * (1.0 + 0.2 * rng.uniform(-1.0, 1.0))
+        R = Rotation.from_rotvec(yaw * np.array([0.0, 1.0, 0.0])).as_matrix()
+        poses.append(poses[-1] @ _rigid(R, np.array([0.0, 0.0, fwd])))
+    sem = 19 if semantic else 0
+    out = []
+    for P in poses:
+        x, u = _render(rng, scene, P, 1241, 376, 700.0, 620.0, 188.0, n, 2.0, 40.0, 5e-4, freq, phase, sem,
+                       stride=2)
+        out.append((x.astype(np.float32), u.astype(np.float32)))
+    spec = [se_block(5, 0.2)] + ([lin_block(19)] if semantic else [])
+    return Sequence("stereo_sequence", out, spec, poses,
+                    first=dict(ell_init=0.95, ell_min=0.1, max_iter=4000),
+                    rest=dict(ell_init=0.1, ell_min=0.1, max_iter=4000))
+
+
 def rgbd_pair(seed=1002, n=40000, m=None, motion=None, ell_init=0.1, ell_min=0.05):
     """TUM-RGB-D-shaped pair: 640x480 grid, f=525, box room 6x4x3 m with 8
     cuboids, depth 0.5-5 m, noise 0.005 d^2, 5 colour+gradient features;

@@ -394,6 +394,33 @@ def test_noise_free_recovery():
     assert np.linalg.norm(E[:3, 3]) < 1e-5
 
 
+def test_odometry_recovers_exact_relative_motions():
+    """Sec. IV frame-to-frame use: frames that are exact rigid copies of one
+    cloud (up to float32 storage) seen from a moving camera; every warm-started
+    pair recovers its relative motion, and the composed trajectory the poses."""
+    rng = np.random.default_rng(41)
+    w = rng.uniform(-1.0, 1.0, (500, 3))
+    u = rng.uniform(0, 1, (500, 5))
+    poses = [np.eye(4)]
+    for _ in range(3):
+        poses.append(poses[-1] @ synth.random_motion(rng, 3.0, 0.06))
+    frames = []
+    for P in poses:
+        Pi = np.linalg.inv(P)
+        frames.append(((w @ Pi[:3, :3].T + Pi[:3, 3]).astype(np.float32), u))
+    prm = dict(ell_init=0.3, ell_min=0.1, max_iter=2000, eps_rot=1e-9, eps_trans=1e-9)
+    rel, reps = oracle.odometry(frames, [synth.se_block(5, 0.3)], prm, prm)
+    acc = np.eye(4)
+    for k, (T, rep) in enumerate(zip(rel, reps)):
+        assert rep["status"] == oracle.CONVERGED
+        E = np.linalg.inv(np.linalg.inv(poses[k]) @ poses[k + 1]) @ T
+        assert np.linalg.norm(Rotation.from_matrix(E[:3, :3]).as_rotvec()) < 1e-5
+        assert np.linalg.norm(E[:3, 3]) < 1e-5
+        acc = acc @ T
+    E = np.linalg.inv(poses[-1]) @ acc
+    assert np.linalg.norm(E[:3, 3]) < 3e-5
+
+
 def test_tiny_cube_fixed_iterations_recovers_motion():
     p = synth.tiny_cube()
     T, rep, tr = oracle.align(p.x, p.u, p.z, p.v, p.spec, p.align)
