@@ -278,6 +278,18 @@ def extras(cvo, torch, synth, dev, nbatch):
                                 cvo.cvo_inner_product_backward(X, Z, q.T_eval, q.ell, 1.0, U, V, q.spec)), 3)
         tot += sec
     ex["forward_backward_ms_per_pair_10k_lin32"] = 1e3 * tot / len(lb)
+    # frame-to-frame odometry: 8 stereo frames of 30k points (7 pairs), the
+    # first from the identity (0.95 -> 0.1), later ones warm-started at 0.1
+    s = synth.stereo_sequence(frames=8)
+    fr = [(torch.from_numpy(x).to(dev), torch.from_numpy(u).to(dev)) for x, u in s.frames]
+    sec, (Ts, reps) = timed(lambda: cvo.cvo_odometry(fr, s.spec, s.first, s.rest), 1)
+    dt, dr = s.drift(list(Ts))
+    ex["odometry_pairs"] = len(Ts)
+    ex["odometry_ms"] = 1e3 * sec
+    ex["odometry_registrations_per_s"] = len(Ts) / sec
+    ex["odometry_warm_iterations_mean"] = float(np.mean([r["iterations"] for r in reps[1:]]))
+    ex["odometry_drift_pct"] = dt
+    ex["odometry_drift_deg_per_m"] = dr
     return ex
 
 

@@ -250,6 +250,21 @@ cvo_status cvo_align_batched(cvo_handle h, int32_t B, const cvo_cloud *X, const 
                              int32_t nparams, const double *T_init, double *T_out,
                              cvo_align_report *reports);
 
+/* Frame-to-frame odometry over a sequence (Sec. IV): pair k (k = 0..F-2)
+ * registers frame k + 1 (moving, Z) to frame k (fixed, X).  Pair 0 starts at
+ * the identity with `first`; pair k > 0 starts at pair k - 1's result with
+ * `rest` (the camera is assumed to keep its motion).  frames: host array of F
+ * clouds (device buffers, all with the spec's feature dimension);
+ * T_rel: host (F-1) x 12 doubles, row k = pose of frame k + 1 in frame k;
+ * reports: host array of F - 1.  The pairs run one after another on the
+ * handle's stream; each result equals the cvo_align call with the same
+ * arguments.  A pair with an empty frame reports CVO_NO_OVERLAP and passes its
+ * start pose on.  F < 2 is CVO_ERR_INVALID_ARGUMENT. */
+cvo_status cvo_odometry(cvo_handle h, int32_t F, const cvo_cloud *frames,
+                        const cvo_feature_spec *spec, const cvo_align_params *first,
+                        const cvo_align_params *rest, double *T_rel,
+                        cvo_align_report *reports);
+
 /* Read / replace the tuning knobs used by later calls. */
 cvo_status cvo_get_tuning(cvo_handle h, cvo_tuning *out);
 cvo_status cvo_set_tuning(cvo_handle h, const cvo_tuning *in);

@@ -31,7 +31,7 @@ MAX_BLOCKS = 8
 
 EXPORTS = ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_last_error", "cvo_inner_product",
            "cvo_gradient", "cvo_evaluate", "cvo_metric", "cvo_cosine", "cvo_align", "cvo_inner_product_backward",
-           "cvo_align_batched", "cvo_get_tuning", "cvo_set_tuning", "cvo_autotune",
+           "cvo_align_batched", "cvo_odometry", "cvo_get_tuning", "cvo_set_tuning", "cvo_autotune",
            "cvo_set_profiling", "cvo_get_timing")
 
 
@@ -116,6 +116,8 @@ def load_library(path: str = LIB_PATH):
     lib.cvo_align_batched.argtypes = [H, C.c_int32, P(cvo_cloud), P(cvo_cloud), P(cvo_feature_spec),
                                       P(cvo_align_params), C.c_int32, C.c_void_p, C.c_void_p,
                                       P(cvo_align_report)]
+    lib.cvo_odometry.argtypes = [H, C.c_int32, P(cvo_cloud), P(cvo_feature_spec), P(cvo_align_params),
+                                 P(cvo_align_params), C.c_void_p, P(cvo_align_report)]
     lib.cvo_get_tuning.argtypes = [H, P(cvo_tuning)]
     lib.cvo_set_tuning.argtypes = [H, P(cvo_tuning)]
     lib.cvo_autotune.argtypes = common + [P(cvo_tuning)]
@@ -358,6 +360,32 @@ def cvo_align_batched(pairs, spec=None, params=None, T_init=None):
     del keep
     Ts = np.tile(np.eye(4), (B, 1, 1))
     Ts[:, :3, :] = Tout.reshape(B, 3, 4)
+    return Ts, [_report(r) for r in reps]
+
+
+def cvo_odometry(frames, spec=None, first=None, rest=None):
+    """Frame-to-frame registration of a sequence [(xyz, feat), ...] of device
+    tensors: pair k registers frame k + 1 to frame k, pair 0 from the identity
+    with `first`, later pairs from the previous estimate with `rest`.
+    Returns (relative poses (F-1, 4, 4), reports)."""
+    h = handle()
+    F = len(frames)
+    D = _dim(spec)
+    fs = (cvo_cloud * F)()
+    keep = []
+    for k, (X, U) in enumerate(frames):
+        fs[k], kk = _cloud(X, U, D, f"frame[{k}]")
+        keep += kk
+    a0, _ = _align_params(first)
+    a1, _ = _align_params(rest)
+    Tout = np.zeros((max(F - 1, 0), 12))
+    reps = (cvo_align_report * max(F - 1, 1))()
+    sp = _spec(spec)
+    _check(load_library().cvo_odometry(h, F, fs, C.byref(sp), C.byref(a0), C.byref(a1), Tout.ctypes.data,
+                                       reps), h)
+    del keep
+    Ts = np.tile(np.eye(4), (F - 1, 1, 1))
+    Ts[:, :3, :] = Tout.reshape(F - 1, 3, 4)
     return Ts, [_report(r) for r in reps]
 
 

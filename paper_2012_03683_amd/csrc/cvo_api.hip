@@ -1263,6 +1263,40 @@ cvo_status cvo_align_batched(cvo_handle h, int32_t B, const cvo_cloud *X, const 
     });
 }
 
+cvo_status cvo_odometry(cvo_handle h, int32_t F, const cvo_cloud *frames, const cvo_feature_spec *spec,
+                        const cvo_align_params *first, const cvo_align_params *rest, double *T_rel,
+                        cvo_align_report *reports)
+{
+    return guarded(h, [&] {
+        require(F >= 2, "a sequence needs at least two frames");
+        require(frames && first && rest && T_rel && reports, "NULL argument");
+        check_spec(spec);
+        const int D = spec_dim(spec);
+        for (int k = 0; k < F; ++k)
+            check_cloud(&frames[k], D, "frame");
+        check_align_params(first);
+        check_align_params(rest);
+        // pair k: frame k fixed, frame k + 1 moving; warm start from pair k - 1
+        double T[12] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0};
+        for (int k = 0; k + 1 < F; ++k) {
+            const cvo_align_params &ap = k == 0 ? *first : *rest;
+            const cvo_cloud *X = &frames[k], *Z = &frames[k + 1];
+            PairState s;
+            if (X->n == 0 || Z->n == 0) {
+                s = init_state(T, ap.ell_init);
+                s.status = ST_NO_OVERLAP;
+            } else {
+                std::vector<PairState> fin;
+                align_many(h, {to_ptrs(X)}, {to_ptrs(Z)}, spec, {ap}, {T}, fin, nullptr, false);
+                s = fin[0];
+            }
+            std::memcpy(T, s.T, sizeof(double) * 12);
+            std::memcpy(T_rel + 12 * k, T, sizeof(double) * 12);
+            fill_report(s, &reports[k]);
+        }
+    });
+}
+
 cvo_status cvo_inner_product_backward(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,
                                       const cvo_feature_spec *spec, const cvo_kernel_params *kp, const double T[12],
                                       double gF, float *dX, float *dZ, float *dU, float *dV, double *dEll)

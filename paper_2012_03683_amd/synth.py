@@ -260,6 +260,19 @@ class Sequence:
         """Ground-truth pose of frame k + 1 in frame k's coordinates."""
         return _inv(self.poses[k]) @ self.poses[k + 1]
 
+    def drift(self, rel):
+        """End-point drift of estimated relative poses rel[k] (frame k + 1 in
+        frame k) chained from frame 0, against the true last pose: translation
+        error in % of the path length and rotation error in deg per m."""
+        T = np.eye(4)
+        for R in rel:
+            T = T @ R
+        G = self.poses[len(rel)]
+        E = _inv(G) @ T
+        path = sum(np.linalg.norm(self.relative(k)[:3, 3]) for k in range(len(rel)))
+        ang = np.degrees(np.arccos(np.clip((np.trace(E[:3, :3]) - 1.0) / 2.0, -1.0, 1.0)))
+        return 100.0 * np.linalg.norm(E[:3, 3]) / path, ang / path
+
 
 def stereo_sequence(seed=1005, frames=8, n=30000, step=1.0, yaw_deg=2.0, semantic=True):
     """Frame-to-frame sequence in the stereo-outdoor scene: the camera moves
