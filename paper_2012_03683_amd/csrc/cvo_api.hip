@@ -770,7 +770,6 @@ struct Problem {
     PairState *d_state = nullptr;
     AlignConst *d_ac = nullptr;
     double *partials = nullptr;
-    unsigned int *counters = nullptr;
     int nblk = 1;
     double kappa = 3.0;
     float sig2 = 1.f;
@@ -803,8 +802,6 @@ void setup_problem(cvo_context *ctx, Problem &p, const std::vector<CloudPtrs> &X
     build_views(ctx, p, X, Z, ell, std::vector<ViewShape>(B, fixed_shape(ctx)));
     p.d_ac = ctx->get_t<AlignConst>("aconst", B);
     ctx->upload(p.d_ac, ac.data(), sizeof(AlignConst) * B);
-    p.counters = ctx->get_t<unsigned int>("counters", B);
-    HIP_OK(hipMemsetAsync(p.counters, 0, sizeof(unsigned int) * B, ctx->stream));
 }
 
 // Kernel arguments of one ascent iteration (pair pass, then reduction).
@@ -823,7 +820,6 @@ void iteration_args(const Problem &p, int mode, double *trace, long long trace_r
     r.state = p.d_state;
     r.ac = p.d_ac;
     r.partials = p.partials;
-    r.counters = p.counters;
     r.trace = trace;
     r.trace_rows = trace_rows;
     r.nblk = p.nblk;

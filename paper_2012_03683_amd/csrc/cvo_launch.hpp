@@ -71,7 +71,6 @@ struct ReduceArgs {
     PairState *state;
     const AlignConst *ac;
     double *partials;          // B * nblk * kRedVals
-    unsigned int *counters;    // B, zero between launches
     double *trace;             // B * trace_rows * kTraceLen, may be null
     long long trace_rows;
     int nblk;

@@ -15,9 +15,9 @@
 //   tr S / ell^3 = dF/dell (cutoff held fixed), |P| = sum n_j,
 //   r_max = max_j |z'_j|.
 // The curvature along a direction d is d^T H d.  Each block reduces a fixed
-// slice of the queries in a fixed tree order; the last block of a pair
-// (atomic ticket) combines the block partials in a fixed order and, in step
-// mode, takes the ascent step -- so results are bitwise reproducible.
+// slice of the queries in a fixed tree order; a second launch, one workgroup
+// per pair, combines the block partials in a fixed order and, in step mode,
+// takes the ascent step -- so results are bitwise reproducible.
 #include "cvo_launch.hpp"
 
 namespace cvo {
@@ -280,13 +280,15 @@ static_assert(kRedThreads == 256 && R_END == 40 && R_END <= kRedVals, "reduction
 __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
 {
     const int b = blockIdx.y;
-    PairState *st = a.state + b;
-    if (st->done || st->pause) return;
+    const PairState *st = a.state + b;
+    // the skip flags, the pose and the cloud range are loaded together (one
+    // round trip) before the skip test
     const ClusterDesc cd = a.cdesc[b];
     double T[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) T[k] = st->T[k];
     const double ell = st->ell;
+    if (st->done | st->pause) return;
     const double ascale = 1.4426950408889634 / (2.0 * ell * ell);
     const double isc = 1.0 / sqrt(ascale), ia = 1.0 / ascale;
     const double il2 = 1.0 / (ell * ell), il4 = il2 * il2;
@@ -395,8 +397,6 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
     // finishes.  Fixed order throughout.
     constexpr int kChunk = 20, kStripes = 8;
     __shared__ double red[kChunk][kRedThreads];
-    __shared__ double tot[R_END];
-    __shared__ int s_last;
     const int tid = threadIdx.x;
     double *part = a.partials + ((long long)b * a.nblk + blockIdx.x) * kRedVals;
     {
@@ -424,18 +424,29 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
             __syncthreads();
         }
     }
-    __threadfence();
-    if (tid == 0) {
-        const unsigned int ticket = atomicAdd(&a.counters[b], 1u);
-        s_last = (ticket == (unsigned int)(a.nblk - 1));
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
+}
 
-    // last block: thread (kv = t / 32, stripe sl = t % 32) adds blocks sl,
-    // sl + 32, ... of the values kv + 8 c, four stripes' loads in flight at
-    // once; a 32-lane shuffle tree finishes.  Fixed order throughout.
+// Second stage, one workgroup per pair: thread (kv = t / 32, stripe sl =
+// t % 32) adds blocks sl, sl + 32, ... of the values kv + 8 c, four stripes'
+// loads in flight at once; a 32-lane shuffle tree finishes, and one thread
+// finishes the pair.  Fixed order throughout.  A separate launch rather than
+// a last-block ticket: the kernel boundary makes the partials visible to
+// every XCD without a device-scope fence in each block of the first stage.
+__global__ __launch_bounds__(kRedThreads) void reduce_finish_kernel(const ReduceArgs a)
+{
+    const int b = blockIdx.x;
+    PairState *st = a.state + b;
+    __shared__ double tot[R_END];
+    const int tid = threadIdx.x;
+    // thread 0 holds the pair's state and constants in registers from the
+    // start, so their loads overlap those of the partials; a skipped pair's
+    // partials are read but not used
+    PairState s;
+    AlignConst ac;
+    if (tid == 0) {
+        s = *st;
+        ac = a.ac[b];
+    }
     const int kv = tid >> 5, sl = tid & 31;
     const double *pb = a.partials + (long long)b * a.nblk * kRedVals;
     double v[R_END / 8];
@@ -467,16 +478,17 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
         if (sl == 0) tot[8 * c + kv] = x;
     }
     __syncthreads();
-    if (tid == 0) {
-        a.counters[b] = 0u;
-        finalize_pair(st, a.ac + b, tot, a.trace ? a.trace + (long long)b * a.trace_rows * kTraceLen : nullptr,
-                      a.trace_rows, a.mode);
+    if (tid == 0 && !(s.done | s.pause)) {
+        finalize_local(s, ac, tot, a.trace ? a.trace + (long long)b * a.trace_rows * kTraceLen : nullptr,
+                       a.trace_rows, a.mode);
+        *st = s;
     }
 }
 
 void launch_reduce(const ReduceArgs &a, int B, hipStream_t s)
 {
     hipLaunchKernelGGL(reduce_kernel, dim3(a.nblk, B), dim3(kRedThreads), 0, s, a);
+    hipLaunchKernelGGL(reduce_finish_kernel, dim3(B), dim3(kRedThreads), 0, s, a);
 }
 
 // ---------------------------------------------------------------- backward
