@@ -1178,7 +1178,9 @@ cvo_status cvo_cosine(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z, cons
         evaluate_one(h, Z, Z, spec, kp, I, &szz);
         const double fxz = (X->n > 0 && Z->n > 0) ? sxz.F : 0.0;
         const double fxx = X->n > 0 ? sxx.F : 0.0, fzz = Z->n > 0 ? szz.F : 0.0;
-        *cos_theta = (fxx > 0.0 && fzz > 0.0) ? fxz / (std::sqrt(fxx) * std::sqrt(fzz)) : 0.0;
+        // sqrt of the product: when the three sums coincide (the moved f_Z is
+        // f_X) the quotient is exactly 1, as sqrt(fl(F * F)) == F
+        *cos_theta = (fxx > 0.0 && fzz > 0.0) ? fxz / std::sqrt(fxx * fzz) : 0.0;
         if (sums) {
             sums[0] = fxz;
             sums[1] = fxx;

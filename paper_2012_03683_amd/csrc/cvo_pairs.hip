@@ -225,8 +225,15 @@ void pair_pass_kernel(const PairPassArgs a)
         // terms per lane) and added to the FP64 accumulators after it.
         auto process = [&](int qn) {
             float w32 = 0.f, dx32 = 0.f, dy32 = 0.f, dz32 = 0.f;
+            // the next candidate's coordinates are read from LDS while this
+            // one is processed (index clamped inside the queue)
+            float4 en = s_xyz[wv][qs];
             for (int k = qs; k < qn; k += SUB) {
-                const float4 e = s_xyz[wv][k];
+                const float4 e = en;
+                {
+                    const int kn = k + SUB;
+                    en = s_xyz[wv][kn < kQueueCap ? kn : kQueueCap - 1];
+                }
                 const float dx = e.x - zrx, dy = e.y - zry, dz = e.z - zrz;
                 const float s = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
                 if (active && s <= hi) {
@@ -240,7 +247,7 @@ void pair_pass_kernel(const PairPassArgs a)
                     }
                     if (pass) {
                         float E = s;
-                        float lin = 0.0f;
+                        float lin = 0.0f, lin1 = 0.0f;  // even / odd LIN columns: two shorter FMA chains
 #pragma unroll
                         for (int f = 0; f < F4; ++f) {
                             const float4 u4 = s_ft[wv][k * F4 + f];
@@ -252,10 +259,12 @@ void pair_pass_kernel(const PairPassArgs a)
                                     const float df = uu[q] - vf[d];
                                     E = fmaf(df, df, E);
                                 } else if (d < D) {
-                                    lin = fmaf(uu[q], vf[d], lin);
+                                    if ((d - SED) & 1) lin1 = fmaf(uu[q], vf[d], lin1);
+                                    else lin = fmaf(uu[q], vf[d], lin);
                                 }
                             }
                         }
+                        lin += lin1;
                         const float wnl = sig2 * __builtin_amdgcn_exp2f(-E);
                         const float w = (LIND > 0) ? wnl * lin : wnl;
                         w32 += w;
