@@ -4,8 +4,10 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The product library never does, and
 this package imports nothing from it.
 
-The arithmetic lives in ``cvo_oracle.c`` (plain C, every operation a rounded
-IEEE double, no FMA); this module only marshals numpy arrays through ctypes.
+The registration arithmetic lives in ``cvo_oracle.c`` (plain C, every
+operation a rounded IEEE double, no FMA); this module only marshals numpy
+arrays through ctypes.  Point selection (``select.py``) is plain integer
+numpy from the FAST definition.
 Feature specs are plain lists of dicts ``{"kind": "se"|"lin", "dim": int,
 "ell": float, "sigma": float}``.
 """
@@ -16,6 +18,8 @@ import os
 import subprocess
 
 import numpy as np
+
+from .select import fast_scores, select_points, select_threshold, valid_depth  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "libcvo_oracle.so")

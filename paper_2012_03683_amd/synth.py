@@ -111,19 +111,23 @@ class _Scene:
         self.planes = []
         self.boxes = []
 
-    def cast(self, o, d):
-        """Nearest hit along rays o + t d (t > 0). Returns t, normal (inf where none)."""
+    def cast(self, o, d, with_id=False):
+        """Nearest hit along rays o + t d (t > 0). Returns t, normal (inf where
+        none) and, if asked, the index of the surface hit (planes first, then
+        boxes; -1 where none)."""
         n = d.shape[0]
         best = np.full(n, np.inf)
         nrm = np.zeros((n, 3))
-        for p0, nv in self.planes:
+        oid = np.full(n, -1)
+        for k, (p0, nv) in enumerate(self.planes):
             den = d @ nv
             with np.errstate(divide="ignore", invalid="ignore"):
                 t = ((p0 - o) @ nv) / den
             ok = (np.abs(den) > 1e-12) & (t > 1e-6) & (t < best)
             best[ok] = t[ok]
             nrm[ok] = nv
-        for lo, hi in self.boxes:
+            oid[ok] = k
+        for k, (lo, hi) in enumerate(self.boxes):
             with np.errstate(divide="ignore", invalid="ignore"):
                 inv = 1.0 / d
                 t0 = (lo - o) * inv
@@ -139,7 +143,8 @@ class _Scene:
                 nn = np.zeros((ok.sum(), 3))
                 nn[np.arange(ok.sum()), ax] = 1.0
                 nrm[ok] = nn
-        return best, nrm
+                oid[ok] = len(self.planes) + k
+        return (best, nrm, oid) if with_id else (best, nrm)
 
 
 def _render(rng, scene, cam, width, height, f, cx, cy, npts, dmin, dmax, noise_k,
@@ -300,6 +305,77 @@ def stereo_sequence(seed=1005, frames=8, n=30000, step=1.0, yaw_deg=2.0, semanti
     return Sequence("stereo_sequence", out, spec, poses,
                     first=dict(ell_init=0.95, ell_min=0.1, max_iter=4000),
                     rest=dict(ell_init=0.1, ell_min=0.1, max_iter=4000))
+
+
+@dataclass
+class ImageFrame:
+    gray: np.ndarray    # H x W uint8 intensity
+    depth: np.ndarray   # H x W float32 (m); 0 where the pixel has no depth
+    feat: np.ndarray    # H x W x D float32 per-pixel features
+
+
+@dataclass
+class ImageSequence:
+    name: str
+    frames: list        # [ImageFrame]
+    camera: dict        # fx, fy, cx, cy, depth_min, depth_max
+    spec: list
+    poses: list         # camera k -> world, 4 x 4
+
+    def relative(self, k):
+        """True pose of frame k + 1 in frame k (maps Z coordinates into X's frame)."""
+        return _inv(self.poses[k]) @ self.poses[k + 1]
+
+
+def stereo_images(seed=1006, frames=2, step=1.0, yaw_deg=2.0, semantic=True, width=1241, height=376):
+    """Full-resolution frames of the stereo-outdoor scene for point selection.
+    Camera as in stereo_pair (f = 700, c = (620, 188)); the camera moves `step`
+    m (+-20%) forward and turns `yaw_deg` (+-30%) per frame.  Grey level =
+    255 x surface albedo (U[0.25, 0.9] per plane or box) x (0.55 or 1.0 on a
+    0.7 m-wavelength checker pattern of two plane waves in world coordinates)
+    + N(0, 1.5), sky 235 + N(0, 1.5), rounded and
+    clipped to uint8.  Depth: ray length along z with noise 5e-4 d^2, 0 where
+    there is no hit.  Features: 5 colour/gradient channels (3 m texture, as in
+    stereo_pair) + 19 Dirichlet(0.3) class probabilities, zero without a hit."""
+    rng = np.random.default_rng(seed)
+    scene = _stereo_scene(rng)
+    freq, phase = _tex_params(rng, 3.0)
+    gfreq, gphase = _tex_params(rng, 0.7)
+    albedo = rng.uniform(0.25, 0.9, len(scene.planes) + len(scene.boxes))
+    f, cx, cy = 700.0, 620.0, 188.0
+    poses = [np.eye(4)]
+    for _ in range(frames - 1):
+        yaw = np.deg2rad(yaw_deg) * (1.0 + 0.3 * rng.uniform(-1.0, 1.0))
+        fwd = step * (1.0 + 0.2 * rng.uniform(-1.0, 1.0))
+        R = Rotation.from_rotvec(yaw * np.array([0.0, 1.0, 0.0])).as_matrix()
+        poses.append(poses[-1] @ _rigid(R, np.array([0.0, 0.0, fwd])))
+    us, vs = np.meshgrid(np.arange(width, dtype=np.float64), np.arange(height, dtype=np.float64))
+    dc = np.stack([(us.ravel() - cx) / f, (vs.ravel() - cy) / f, np.ones(us.size)], axis=1)
+    sem = 19 if semantic else 0
+    out = []
+    for P in poses:
+        dw = dc @ P[:3, :3].T
+        o = np.broadcast_to(P[:3, 3], dw.shape)
+        dep, nrm, oid = scene.cast(o, dw, with_id=True)
+        hit = np.isfinite(dep)
+        pw = o[hit] + dep[hit, None] * dw[hit]
+        arg = pw @ gfreq[:2].T + gphase[:2]
+        shade = 0.55 + 0.45 * ((np.sin(arg[:, 0]) > 0) ^ (np.sin(arg[:, 1]) > 0))
+        g = np.full(us.size, 235.0)
+        g[hit] = 255.0 * albedo[oid[hit]] * shade
+        g += rng.normal(0.0, 1.5, us.size)
+        gray = np.clip(np.rint(g), 0, 255).astype(np.uint8).reshape(height, width)
+        d = np.zeros(us.size)
+        d[hit] = dep[hit] + rng.normal(0.0, 1.0, hit.sum()) * 5e-4 * dep[hit] ** 2
+        feat = np.zeros((us.size, 5 + sem), np.float32)
+        feat[hit, :5] = _colour_features(rng, pw, nrm[hit], freq, phase)
+        if sem:
+            feat[hit, 5:] = rng.dirichlet(np.full(sem, 0.3), size=int(hit.sum()))
+        out.append(ImageFrame(gray, d.astype(np.float32).reshape(height, width),
+                              feat.reshape(height, width, 5 + sem)))
+    spec = [se_block(5, 0.2)] + ([lin_block(19)] if semantic else [])
+    cam = dict(fx=f, fy=f, cx=cx, cy=cy, depth_min=2.0, depth_max=40.0)
+    return ImageSequence("stereo_images", out, cam, spec, poses)
 
 
 def rgbd_pair(seed=1002, n=40000, m=None, motion=None, ell_init=0.1, ell_min=0.05):
