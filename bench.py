@@ -290,6 +290,21 @@ def extras(cvo, torch, synth, dev, nbatch):
     ex["odometry_warm_iterations_mean"] = float(np.mean([r["iterations"] for r in reps[1:]]))
     ex["odometry_drift_pct"] = dt
     ex["odometry_drift_deg_per_m"] = dr
+    # point selection on full 1241 x 376 stereo frames (24 feature channels),
+    # at most 15000 points, then registration of the two selected clouds
+    s = synth.stereo_images(frames=2)
+    imgs = [tuple(torch.from_numpy(a).to(dev) for a in (f.gray, f.depth, f.feat)) for f in s.frames]
+    sec, (xyz, fo, th, _) = timed(lambda: cvo.cvo_select_points(*imgs[0], s.camera, 15000), 20)
+    ex["select_ms_per_frame"] = 1e3 * sec
+    ex["select_points"] = int(xyz.shape[0])
+    ex["select_threshold"] = th
+    sel = [cvo.cvo_select_points(*im, s.camera, 15000)[:2] for im in imgs]
+    prm = dict(ell_init=0.95, ell_min=0.1, max_iter=4000)
+    sec, (T, rep, _) = timed(lambda: cvo.cvo_align(sel[0][0], sel[1][0], sel[0][1], sel[1][1], s.spec, prm), 3)
+    R = np.linalg.inv(s.relative(0)) @ T
+    ex["selected_registration_ms"] = 1e3 * sec
+    ex["selected_registration_rot_err_deg"] = float(np.degrees(np.arccos(np.clip((np.trace(R[:3, :3]) - 1) / 2, -1, 1))))
+    ex["selected_registration_trans_err_m"] = float(np.linalg.norm(R[:3, 3]))
     return ex
 
 

@@ -265,6 +265,39 @@ cvo_status cvo_odometry(cvo_handle h, int32_t F, const cvo_cloud *frames,
                         const cvo_align_params *rest, double *T_rel,
                         cvo_align_report *reports);
 
+/* Pinhole camera of a depth image: pixel (u, v) with depth z back-projects to
+ * ((u - cx) z / fx, (v - cy) z / fy, z).  A pixel has depth when its value is
+ * finite and within [depth_min, depth_max] (compared in FP32). */
+typedef struct {
+    double fx, fy, cx, cy;       /* pixels; fx, fy > 0 */
+    double depth_min, depth_max; /* metres; 0 < depth_min <= depth_max, finite */
+} cvo_camera;
+
+/* Point selection before registration (Sec. V, performance considerations):
+ * pixels that pass the FAST segment test (an arc of >= 9 contiguous pixels of
+ * the radius-3 circle all brighter than I_p + t or all darker than I_p - t;
+ * pixels within 3 of the border are never selected), no non-maximum
+ * suppression, with depth.  The threshold t is chosen per call as the
+ * smallest integer whose selection holds at most max_points pixels (the paper
+ * keeps 3k-15k; a score histogram gives every count at once).
+ *   gray:  device, height x width uint8, row-major.
+ *   depth: device, height x width float32 (metres).
+ *   feat:  device, height x width x D float32 per-pixel features (NULL if D = 0).
+ *   xyz, feat_out: device, capacity x 3 and capacity x D float32; rows
+ *          0..n-1 receive the selected pixels in raster order (camera-frame
+ *          points as in cvo_camera, FP64 arithmetic rounded to FP32; feature
+ *          rows copied).  capacity must be >= max_points.
+ *   score: device, height x width int16, or NULL: each pixel's score, the
+ *          largest t at which it passes the test (-1: none).
+ *   n_out, threshold_out: host.
+ * Synchronises the handle's stream.  Errors: CVO_ERR_INVALID_ARGUMENT for
+ * NULL buffers that are needed, width or height < 0, width x height >= 2^31,
+ * D outside [0, 256], a bad camera, max_points < 0 or capacity < max_points. */
+cvo_status cvo_select_points(cvo_handle h, const uint8_t *gray, const float *depth, const float *feat,
+                             int32_t width, int32_t height, int32_t D, const cvo_camera *cam,
+                             int32_t max_points, float *xyz, float *feat_out, int64_t capacity,
+                             int16_t *score, int64_t *n_out, int32_t *threshold_out);
+
 /* Read / replace the tuning knobs used by later calls. */
 cvo_status cvo_get_tuning(cvo_handle h, cvo_tuning *out);
 cvo_status cvo_set_tuning(cvo_handle h, const cvo_tuning *in);

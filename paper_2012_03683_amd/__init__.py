@@ -31,7 +31,7 @@ MAX_BLOCKS = 8
 
 EXPORTS = ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_last_error", "cvo_inner_product",
            "cvo_gradient", "cvo_evaluate", "cvo_metric", "cvo_cosine", "cvo_align", "cvo_inner_product_backward",
-           "cvo_align_batched", "cvo_odometry", "cvo_get_tuning", "cvo_set_tuning", "cvo_autotune",
+           "cvo_align_batched", "cvo_odometry", "cvo_select_points", "cvo_get_tuning", "cvo_set_tuning", "cvo_autotune",
            "cvo_set_profiling", "cvo_get_timing")
 
 
@@ -79,6 +79,11 @@ class cvo_tuning(C.Structure):
                 ("adaptive", C.c_int32)]
 
 
+class cvo_camera(C.Structure):
+    _fields_ = [("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+                ("depth_min", C.c_double), ("depth_max", C.c_double)]
+
+
 class cvo_timing(C.Structure):
     _fields_ = [("pair_launches", C.c_int64), ("pair_ms", C.c_double), ("pair_count", C.c_int64),
                 ("evaluations", C.c_int64)]
@@ -118,6 +123,9 @@ def load_library(path: str = LIB_PATH):
                                       P(cvo_align_report)]
     lib.cvo_odometry.argtypes = [H, C.c_int32, P(cvo_cloud), P(cvo_feature_spec), P(cvo_align_params),
                                  P(cvo_align_params), C.c_void_p, P(cvo_align_report)]
+    lib.cvo_select_points.argtypes = [H, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                      P(cvo_camera), C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                      P(C.c_int64), P(C.c_int32)]
     lib.cvo_get_tuning.argtypes = [H, P(cvo_tuning)]
     lib.cvo_set_tuning.argtypes = [H, P(cvo_tuning)]
     lib.cvo_autotune.argtypes = common + [P(cvo_tuning)]
@@ -387,6 +395,49 @@ def cvo_odometry(frames, spec=None, first=None, rest=None):
     Ts = np.tile(np.eye(4), (F - 1, 1, 1))
     Ts[:, :3, :] = Tout.reshape(F - 1, 3, 4)
     return Ts, [_report(r) for r in reps]
+
+
+def _dev_image(t, dtype, shape, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} is on {t.device}; the CVO library has no CPU path")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}")
+    return t.contiguous()
+
+
+def cvo_select_points(gray, depth, feat=None, camera=None, max_points=15000, scores=False):
+    """Point selection on device images (FAST 9-of-16, threshold chosen so at
+    most max_points pixels with depth are kept).  gray (H, W) uint8, depth
+    (H, W) float32, feat (H, W, D) float32 or None, camera a dict of fx, fy,
+    cx, cy, depth_min, depth_max.  Returns (xyz (n, 3), feat (n, D),
+    threshold, scores (H, W) int16 or None)."""
+    torch = _torch()
+    h = handle()
+    H, W = gray.shape
+    gray = _dev_image(gray, torch.uint8, (H, W), "gray")
+    depth = _dev_image(depth, torch.float32, (H, W), "depth")
+    D = 0 if feat is None else int(feat.shape[-1])
+    if D:
+        feat = _dev_image(feat, torch.float32, (H, W, D), "feat")
+    cam = cvo_camera(camera["fx"], camera["fy"], camera["cx"], camera["cy"], camera["depth_min"],
+                     camera["depth_max"])
+    cap = int(max_points)
+    xyz = torch.empty((cap, 3), dtype=torch.float32, device=gray.device)
+    fo = torch.empty((cap, D), dtype=torch.float32, device=gray.device)
+    sc = torch.empty((H, W), dtype=torch.int16, device=gray.device) if scores else None
+    n = C.c_int64()
+    t = C.c_int32()
+    ptr = (lambda x: x.data_ptr() if (x is not None and x.numel()) else None)
+    _check(load_library().cvo_select_points(h, ptr(gray), ptr(depth), ptr(feat) if D else None, W, H, D,
+                                            C.byref(cam), cap, ptr(xyz), ptr(fo), cap, ptr(sc), C.byref(n),
+                                            C.byref(t)), h)
+    k = int(n.value)
+    return xyz[:k], fo[:k], int(t.value), sc
 
 
 def cvo_inner_product_backward(X, Z, T, ell, gF=1.0, U=None, V=None, spec=None, sigma=1.0, kappa=3.0,

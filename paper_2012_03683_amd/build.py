@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcvo_hip.so")
-SOURCES = ["cvo_build.hip", "cvo_pairs.hip", "cvo_reduce.hip", "cvo_api.hip"]
+SOURCES = ["cvo_build.hip", "cvo_pairs.hip", "cvo_reduce.hip", "cvo_select.hip", "cvo_api.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -1295,6 +1295,65 @@ cvo_status cvo_odometry(cvo_handle h, int32_t F, const cvo_cloud *frames, const 
     });
 }
 
+cvo_status cvo_select_points(cvo_handle h, const uint8_t *gray, const float *depth, const float *feat,
+                             int32_t width, int32_t height, int32_t D, const cvo_camera *cam, int32_t max_points,
+                             float *xyz, float *feat_out, int64_t capacity, int16_t *score, int64_t *n_out,
+                             int32_t *threshold_out)
+{
+    return guarded(h, [&] {
+        require(cam && n_out && threshold_out, "NULL argument");
+        require(width >= 0 && height >= 0, "width and height must be >= 0");
+        const long long npix = (long long)width * height;
+        require(npix < (1LL << 31), "width x height must be < 2^31");
+        require(D >= 0 && D <= 256, "D must be in [0, 256]");
+        require(std::isfinite(cam->fx) && std::isfinite(cam->fy) && cam->fx > 0.0 && cam->fy > 0.0,
+                "fx and fy must be finite and > 0");
+        require(std::isfinite(cam->cx) && std::isfinite(cam->cy), "cx and cy must be finite");
+        require(std::isfinite(cam->depth_min) && std::isfinite(cam->depth_max) && cam->depth_min > 0.0 &&
+                    cam->depth_min <= cam->depth_max,
+                "need 0 < depth_min <= depth_max, both finite");
+        require(max_points >= 0 && capacity >= max_points, "need 0 <= max_points <= capacity");
+        require(npix == 0 || (gray && depth), "gray / depth is NULL");
+        require(npix == 0 || D == 0 || feat, "feat is NULL");
+        require(max_points == 0 || xyz, "xyz is NULL");
+        require(max_points == 0 || D == 0 || feat_out, "feat_out is NULL");
+        *n_out = 0;
+        *threshold_out = 0;
+        if (npix == 0) return;
+        const int nb = select_blocks(npix);
+        SelectArgs a{};
+        a.gray = gray;
+        a.depth = depth;
+        a.feat = feat;
+        a.W = width;
+        a.H = height;
+        a.D = D;
+        a.dmin = (float)cam->depth_min;
+        a.dmax = (float)cam->depth_max;
+        a.fx = cam->fx;
+        a.fy = cam->fy;
+        a.cx = cam->cx;
+        a.cy = cam->cy;
+        a.cap = max_points;
+        a.key = h->get_t<short>("sel.key", npix);
+        a.score = score;
+        a.hist = h->get_t<int>("sel.hist", 256);
+        a.res = h->get_t<int>("sel.res", 2);
+        a.bcount = h->get_t<int>("sel.bcount", nb);
+        a.boff = h->get_t<int>("sel.boff", nb);
+        a.bsum = h->get_t<int>("sel.bsum", nb / 2048 + 2);
+        a.xyz = xyz;
+        a.fout = feat_out;
+        HIP_OK(hipMemsetAsync(a.hist, 0, 256 * sizeof(int), h->stream));
+        launch_select(a, h->stream);
+        h->check_launch("point selection");
+        int res[2];
+        h->download(res, a.res, sizeof(res));
+        *threshold_out = res[0];
+        *n_out = res[1];
+    });
+}
+
 cvo_status cvo_inner_product_backward(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,
                                       const cvo_feature_spec *spec, const cvo_kernel_params *kp, const double T[12],
                                       double gF, float *dX, float *dZ, float *dU, float *dV, double *dEll)

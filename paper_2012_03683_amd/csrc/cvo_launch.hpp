@@ -93,6 +93,26 @@ struct BackwardArgs {
     long long n;
 };
 void launch_backward_finish(const BackwardArgs &a, hipStream_t s);
+
+// point selection (FAST scores, threshold, raster-order compaction)
+struct SelectArgs {
+    const uint8_t *gray;   // H x W
+    const float *depth;    // H x W
+    const float *feat;     // H x W x D (may be null if D == 0)
+    int W, H, D;
+    float dmin, dmax;      // valid depth range, compared in FP32
+    double fx, fy, cx, cy;
+    int cap;               // largest selection allowed
+    short *key;            // H x W scratch: score if the pixel has depth, else -1
+    short *score;          // H x W scores for the caller (may be null)
+    int *hist;             // 256, zero on entry
+    int *res;              // (threshold, count)
+    int *bcount, *boff, *bsum;  // per 256-pixel block counts, their exclusive scan, scan scratch
+    float *xyz;            // cap x 3
+    float *fout;           // cap x D
+};
+void launch_select(const SelectArgs &a, hipStream_t s);
+int select_blocks(long long npix);
 void launch_sum_doubles(const double *in, long long n, double *out, hipStream_t s);
 
 }  // namespace cvo

@@ -19,7 +19,7 @@ def declared():
 
 def test_header_declares_the_entry_points():
     names = declared()
-    for must in ("cvo_inner_product", "cvo_gradient", "cvo_align", "cvo_metric", "cvo_cosine", "cvo_odometry",
+    for must in ("cvo_inner_product", "cvo_gradient", "cvo_align", "cvo_metric", "cvo_cosine", "cvo_odometry", "cvo_select_points",
                  "cvo_inner_product_backward", "cvo_align_batched", "cvo_create", "cvo_destroy"):
         assert must in names
 
@@ -51,6 +51,7 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(cvo.cvo_align_report) == 56
     assert ctypes.sizeof(cvo.cvo_eval) == 8 * 12
     assert ctypes.sizeof(cvo.cvo_tuning) == 48
+    assert ctypes.sizeof(cvo.cvo_camera) == 48
 
 
 def test_product_path_refuses_cpu_tensors():
