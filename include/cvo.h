@@ -153,8 +153,10 @@ typedef struct {
     int32_t piece_work;    /* query x candidate products per unit of pair-pass work, 256..2^24 */
     int32_t adaptive;      /* 0 or 1.  1: a registration re-chooses cluster_max, cell_factor and
                             * cluster_factor at every view build from the in-cutoff pairs per query point
-                            * of its latest iteration: >= 2000: 64, 0.5, 0.5; >= 500: 32, 0.5, 0.5;
-                            * >= 100: 32, 1.0, 1.5; fewer: 16, 1.0, 1.5; not yet measured: the three
+                            * of its latest iteration.  Padded feature rows of more than 8 floats:
+                            * >= 2000: 64, 0.5, 0.5; >= 500: 32, 0.5, 0.5; >= 200: 32, 1.0, 1.5;
+                            * fewer: 16, 1.0, 1.0.  Rows of at most 8 floats: >= 500: 64, 0.5, 0.5;
+                            * >= 100: 32, 1.0, 1.5; fewer: 16, 1.0, 1.5.  Not yet measured: the three
                             * fields above.  One-shot calls always use the fields above. */
 } cvo_tuning;
 

@@ -364,19 +364,32 @@ ViewShape fixed_shape(const cvo_context *ctx)
     return ViewShape{ctx->tuning.cluster_max, ctx->tuning.cell_factor, ctx->tuning.cluster_factor};
 }
 
-// Shape for a density class (density_class of the in-cutoff pairs per query
-// point; -1 when unknown).  Dense bands amortise each candidate load over
-// more queries and cut the neighbourhood finer; sparse bands, where a
-// cluster holds a few points, let clusters grow to 1.5 cutoff radii so a
-// wave's fixed cost is shared by more queries.
-ViewShape density_shape(const cvo_context *ctx, int cls)
+// Density classes and their view shapes, measured per feature layout.  Dense
+// bands amortise each candidate load over more queries and cut the
+// neighbourhood finer; sparse bands, where a cluster holds a few points, let
+// clusters grow past the cutoff radius so a wave's fixed cost is shared by
+// more queries.  Rows of at most 8 floats (cheap pairs) favour large clusters
+// down to 500 pairs per query (classes 3 and 2 merged); wider rows (costly
+// pairs, where every culled lane wastes more) switch to 16-point clusters
+// below 200.
+bool light_layout(const FeatLayout &lay) { return lay.d4 <= 8; }
+
+void class_thresholds(const FeatLayout &lay, double t[3])
+{
+    t[0] = light_layout(lay) ? INFINITY : 2000.0;
+    t[1] = 500.0;
+    t[2] = light_layout(lay) ? 100.0 : 200.0;
+}
+
+ViewShape density_shape(const cvo_context *ctx, int cls, const FeatLayout &lay)
 {
     if (!ctx->tuning.adaptive) return fixed_shape(ctx);
+    const bool light = light_layout(lay);
     switch (cls) {
     case 3: return ViewShape{64, 0.5, 0.5};
-    case 2: return ViewShape{32, 0.5, 0.5};
+    case 2: return light ? ViewShape{64, 0.5, 0.5} : ViewShape{32, 0.5, 0.5};
     case 1: return ViewShape{32, 1.0, 1.5};
-    case 0: return ViewShape{16, 1.0, 1.5};
+    case 0: return light ? ViewShape{16, 1.0, 1.5} : ViewShape{16, 1.0, 1.0};
     default: return fixed_shape(ctx);
     }
 }
@@ -889,6 +902,7 @@ AlignConst const_for(const cvo_align_params *ap, long long N, long long M)
     }
     a.rebuild_ratio = 1.0;
     a.adaptive = 0;
+    a.cls_t[0] = a.cls_t[1] = a.cls_t[2] = INFINITY;
     a.sqrt_nm = std::sqrt((double)N * (double)M);
     a.inv_m = M > 0 ? 1.0 / (double)M : 0.0;
     return a;
@@ -983,6 +997,7 @@ void align_many(cvo_context *ctx, const std::vector<CloudPtrs> &X, const std::ve
         ac[b] = const_for(&prm[b], X[b].n, Z[b].n);
         ac[b].rebuild_ratio = ctx->tuning.rebuild_ratio;
         ac[b].adaptive = adapt ? 1 : 0;
+        class_thresholds(p.lay, ac[b].cls_t);
         if (X[b].n == 0 || Z[b].n == 0) {
             st[b].status = ST_NO_OVERLAP;
             st[b].done = 1;
@@ -1035,8 +1050,8 @@ void align_many(cvo_context *ctx, const std::vector<CloudPtrs> &X, const std::ve
             if (now[b].done) continue;
             all_done = false;
             if (!probe && !now[b].pause) continue;
-            const int cls = adapt ? density_class(now[b].n_pairs / (double)std::max(Z[b].n, 1LL)) : -1;
-            const ViewShape want = adapt ? density_shape(ctx, cls) : fixed_shape(ctx);
+            const int cls = adapt ? density_class(now[b].n_pairs / (double)std::max(Z[b].n, 1LL), ac[b].cls_t) : -1;
+            const ViewShape want = adapt ? density_shape(ctx, cls, p.lay) : fixed_shape(ctx);
             if (now[b].pause || !(want == p.shape[b])) {
                 rebuild = true;
                 ell_build[b] = now[b].ell;

@@ -53,10 +53,10 @@ struct alignas(16) PairState {
 };
 
 // Density class of an evaluation from its in-cutoff pairs per query point
-// (-1: unknown): 3 from 2000, 2 from 500, 1 from 100, else 0.
-__host__ __device__ inline int density_class(double ppq)
+// (-1: unknown): 3 from t[0], 2 from t[1], 1 from t[2], else 0.
+__host__ __device__ inline int density_class(double ppq, const double t[3])
 {
-    return !(ppq >= 0.0) ? -1 : (ppq >= 2000.0 ? 3 : (ppq >= 500.0 ? 2 : (ppq >= 100.0 ? 1 : 0)));
+    return !(ppq >= 0.0) ? -1 : (ppq >= t[0] ? 3 : (ppq >= t[1] ? 2 : (ppq >= t[2] ? 1 : 0)));
 }
 
 // Per-pair constants of the ascent.
@@ -70,6 +70,7 @@ struct alignas(16) AlignConst {
     int fixed_iters;
     int metric;          // 0: kinetic-energy metric of the moving cloud, 1: identity
     int adaptive;        // nonzero: also pause when the density class drops below cls_built
+    double cls_t[3];     // pairs per query where density classes 3, 2 and 1 begin
 };
 
 // Uniform grid of one cloud (reference role).

@@ -263,7 +263,7 @@ __device__ __forceinline__ void finalize_local(PairState &st, const AlignConst &
     // alone, so where views change does not depend on how many iterations
     // are enqueued between host checks.
     if (isfinite(ac.kappa) && ac.kappa * st.ell < ac.rebuild_ratio * st.rc_build) st.pause = 1;
-    if (ac.adaptive && st.cls_built >= 0 && density_class(np * ac.inv_m) < st.cls_built) st.pause = 1;
+    if (ac.adaptive && st.cls_built >= 0 && density_class(np * ac.inv_m, ac.cls_t) < st.cls_built) st.pause = 1;
 }
 
 __device__ void finalize_pair(PairState *st_g, const AlignConst *ac_g, const double *tot, double *trace,
