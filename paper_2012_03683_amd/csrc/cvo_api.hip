@@ -107,21 +107,47 @@ struct cvo_context {
         }
         return pinned;
     }
-    // copy host -> device through pinned memory and wait (setup-time only)
+    // Host -> device copies are staged in a pinned ring and not waited for.
+    // A ring slot is written again only after the stream that reads it has
+    // been synchronised (the ring restarts then), so a pending copy never
+    // sees its source change.
+    void *ring = nullptr;
+    size_t ring_cap = 0, ring_off = 0;
+    hipStream_t ring_stream = nullptr;
+    void ring_drain()
+    {
+        if (ring_off) {
+            HIP_OK(hipStreamSynchronize(ring_stream));
+            ring_off = 0;
+        }
+    }
     void upload(void *dst, const void *src, size_t bytes)
     {
         if (!bytes) return;
-        void *h = host(bytes);
+        const size_t need = (bytes + 255) & ~size_t(255);
+        if (ring_off && (ring_stream != stream || ring_off + need > ring_cap)) ring_drain();
+        if (need > ring_cap) {
+            if (ring) HIP_OK(hipHostFree(ring));
+            ring = nullptr;
+            ring_cap = 0;
+            const size_t cap = std::max(need, size_t(1) << 20);
+            HIP_OK(hipHostMalloc(&ring, cap, hipHostMallocDefault));
+            ring_cap = cap;
+        }
+        char *h = static_cast<char *>(ring) + ring_off;
         std::memcpy(h, src, bytes);
         HIP_OK(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, stream));
-        HIP_OK(hipStreamSynchronize(stream));
+        ring_off += need;
+        ring_stream = stream;
     }
+    // device -> host, waiting for the stream (which also frees the ring)
     void download(void *dst, const void *src, size_t bytes)
     {
         if (!bytes) return;
         void *h = host(bytes);
         HIP_OK(hipMemcpyAsync(h, src, bytes, hipMemcpyDeviceToHost, stream));
         HIP_OK(hipStreamSynchronize(stream));
+        if (stream == ring_stream) ring_off = 0;
         std::memcpy(dst, h, bytes);
     }
     void check_launch(const char *what)
@@ -168,6 +194,9 @@ struct cvo_context {
         bufs.clear();
         if (pinned) hipHostFree(pinned);
         pinned = nullptr;
+        if (ring) hipHostFree(ring);
+        ring = nullptr;
+        ring_off = ring_cap = 0;
         for (auto &pr : ev_pending) {
             hipEventDestroy(pr.first);
             hipEventDestroy(pr.second);
@@ -965,6 +994,7 @@ template <class F> cvo_status guarded(cvo_context *ctx, F &&f)
     try {
         HIP_OK(hipSetDevice(ctx->device));
         (void)hipGetLastError();  // drop any error left by an earlier failure
+        ctx->ring_drain();        // copies an earlier, failed call may have left in flight
         f();
         return CVO_OK;
     } catch (const CvoError &e) {
@@ -1114,6 +1144,7 @@ void cvo_destroy(cvo_handle h)
     if (!h) return;
     hipSetDevice(h->device);
     if (h->stream) hipStreamSynchronize(h->stream);
+    if (h->ring_off) hipStreamSynchronize(h->ring_stream);
     h->release();
     delete h;
 }
