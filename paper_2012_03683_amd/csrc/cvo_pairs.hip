@@ -225,17 +225,17 @@ void pair_pass_kernel(const PairPassArgs a)
         // terms per lane) and added to the FP64 accumulators after it.
         auto process = [&](int qn) {
             float w32 = 0.f, dx32 = 0.f, dy32 = 0.f, dz32 = 0.f;
-            // the next candidate's coordinates are read from LDS while this
-            // one is processed (index clamped inside the queue)
-            float4 en = s_xyz[wv][qs];
+            // the next candidate's coordinates are read from LDS as soon as
+            // this one's distance is known, so the read overlaps the rest of
+            // the iteration (index clamped inside the queue)
+            float4 e = s_xyz[wv][qs];
             for (int k = qs; k < qn; k += SUB) {
-                const float4 e = en;
-                {
-                    const int kn = k + SUB;
-                    en = s_xyz[wv][kn < kQueueCap ? kn : kQueueCap - 1];
-                }
                 const float dx = e.x - zrx, dy = e.y - zry, dz = e.z - zrz;
                 const float s = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                {
+                    const int kn = k + SUB;
+                    e = s_xyz[wv][kn < kQueueCap ? kn : kQueueCap - 1];
+                }
                 if (active && s <= hi) {
                     bool pass = true;
                     if (s > lo) {
