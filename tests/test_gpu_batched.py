@@ -63,3 +63,31 @@ def test_batched_with_empty_and_fixed_pairs(cvo):
     for T1, T2 in ((Ts[0], Ta), (Ts[1], Tb_)):
         ang, tr = pose_error(T1, T2)
         assert ang < 1e-9 and tr < 1e-9
+
+
+def test_batched_full_size_pairs_match_plain(cvo):
+    """The first 8 pairs of the 64-pair batched workload at their real sizes
+    (N, M ~ U[2000, 60000], mixed stereo / RGB-D, 5 SE + 19 LIN): one batched
+    call against 8 plain registrations (poses within 1e-4 rad / 1e-4 m), and
+    one oracle evaluation at the final pose of the two smallest pairs (exact
+    |P|, F and gradient within 1e-5 of their absolute sums)."""
+    from gpu_util import assert_eval_matches
+    pairs = synth.batched_pairs(seed=1004, batch=8)
+    tens = [_dev(q) for q in pairs]
+    prm = [q.align for q in pairs]
+    print("sizes", [(q.x.shape[0], q.z.shape[0]) for q in pairs], flush=True)
+    Tb, rb = cvo.cvo_align_batched(tens, pairs[0].spec, prm)
+    for k, (q, t) in enumerate(zip(pairs, tens)):
+        Tp, rp, _ = cvo.cvo_align(*t, q.spec, q.align)
+        ang, tr = pose_error(Tb[k], Tp)
+        print(q.name, rb[k]["iterations"], rp["iterations"], ang, tr, flush=True)
+        assert rb[k]["status"] == rp["status"] == cvo.CVO_CONVERGED
+        assert rb[k]["final_ell"] == rp["final_ell"]
+        assert ang < 1e-4 and tr < 1e-4
+    small = sorted(range(len(pairs)), key=lambda k: pairs[k].x.shape[0] * pairs[k].z.shape[0])[:2]
+    for k in small:
+        q = pairs[k]
+        ell = rb[k]["final_ell"]
+        g = cvo.cvo_evaluate(*tens[k][:2], Tb[k], ell, *tens[k][2:], q.spec)
+        o = oracle.evaluate(q.x, q.u, q.z, q.v, q.spec, ell, T=Tb[k])
+        assert_eval_matches(g, o, what=q.name)
