@@ -741,8 +741,6 @@ PairPassArgs pass_args(const ClusterView &q, const GridView &r, const PairState 
     a.oCnt = m.cnt;
     a.oG = m.G;
     a.oL = m.L;
-    a.pieces = pl.pieces;
-    a.porder = pl.porder;
     a.recs = pl.recs;
     a.npieces = pl.npieces;
     return a;

@@ -123,9 +123,7 @@ struct PairPassArgs {
     const double4 *cgeo;  // (centre xyz in the query frame, radius)
     const int *cpair;     // pair of each cluster
     int nclus;
-    const int4 *pieces;   // (cluster, piece index p, pieces np, first output slot), cluster-major
-    const int *porder;    // processing order of the pieces: heaviest first
-    const PieceRec *recs; // the pieces in processing order, with their cluster data
+    const PieceRec *recs; // the pieces in processing order (heaviest first), with their cluster data
     int npieces;
     // reference side (grid view)
     const float4 *rpts;

@@ -265,7 +265,8 @@ void pair_pass_kernel(const PairPassArgs a)
                             }
                         }
                         lin += lin1;
-                        const float wnl = sig2 * __builtin_amdgcn_exp2f(-E);
+                        // sigma^2 prod sigma_b^2 is applied once per query at the end
+                        const float wnl = __builtin_amdgcn_exp2f(-E);
                         const float w = (LIND > 0) ? wnl * lin : wnl;
                         w32 += w;
                         const float wx = w * dx, wy = w * dy, wz = w * dz;
@@ -404,18 +405,20 @@ void pair_pass_kernel(const PairPassArgs a)
         }
         if (qs == 0 && active) {
             const long long o = (long long)pc.w + t;
-            a.oW[o] = W;
-            a.oD[3 * o + 0] = Dx;
-            a.oD[3 * o + 1] = Dy;
-            a.oD[3 * o + 2] = Dz;
+            const double sg = (double)sig2;  // every output is linear in the kernel weights
+            a.oW[o] = sg * W;
+            a.oD[3 * o + 0] = sg * Dx;
+            a.oD[3 * o + 1] = sg * Dy;
+            a.oD[3 * o + 2] = sg * Dz;
             a.oCnt[o] = cnt;
             if (MODE == 0) {
                 float *S = a.oS + 6 * o;
-                S[0] = S00; S[1] = S01; S[2] = S02; S[3] = S11; S[4] = S12; S[5] = S22;
+                S[0] = sig2 * S00; S[1] = sig2 * S01; S[2] = sig2 * S02;
+                S[3] = sig2 * S11; S[4] = sig2 * S12; S[5] = sig2 * S22;
             } else {
-                a.oL[o] = Ls;
+                a.oL[o] = sg * Ls;
 #pragma unroll
-                for (int k = 0; k < (MODE == 1 ? D4 : 0); ++k) a.oG[o * D4 + k] = Gf[k];
+                for (int k = 0; k < (MODE == 1 ? D4 : 0); ++k) a.oG[o * D4 + k] = sg * Gf[k];
             }
         }
     }
