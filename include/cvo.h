@@ -275,7 +275,7 @@ typedef struct {
     double depth_min, depth_max; /* metres; 0 < depth_min <= depth_max, finite */
 } cvo_camera;
 
-/* Point selection before registration (Sec. V, performance considerations):
+/* Point selection before registration (Sec. IV, performance considerations):
  * pixels that pass the FAST segment test (an arc of >= 9 contiguous pixels of
  * the radius-3 circle all brighter than I_p + t or all darker than I_p - t;
  * pixels within 3 of the border are never selected), no non-maximum

@@ -1,4 +1,4 @@
-"""Point selection before registration (Sec. V's performance considerations:
+"""Point selection before registration (Sec. IV, considerations for performance:
 FAST corners, no non-maximum suppression, threshold chosen automatically so
 that a few thousand pixels with depth are kept) -- TEST INFRASTRUCTURE ONLY.
 

@@ -1,5 +1,5 @@
 // cvo_select.hip -- point selection before registration (the paper's
-// performance considerations, Sec. V): pixels passing the FAST 9-of-16
+// performance considerations, Sec. IV): pixels passing the FAST 9-of-16
 // segment test, no non-maximum suppression, with the intensity threshold
 // chosen so that the number of selected pixels with depth stays within a cap;
 // the selection is compacted in raster order and back-projected.

@@ -1,5 +1,5 @@
 """GPU parity of point selection (FAST 9-of-16 segment test, automatic
-threshold, raster-order back-projection; Sec. V's performance
+threshold, raster-order back-projection; Sec. IV's performance
 considerations) against the oracle, through the C ABI: scores, threshold,
 count and selected pixels bit for bit, points and features exactly."""
 import ctypes

@@ -1,5 +1,5 @@
 """Pins of the point-selection oracle (FAST segment test with an automatic
-threshold, Sec. V's performance considerations) against what the definition
+threshold, Sec. IV's performance considerations) against what the definition
 fixes: a literal run-length segment test on small images, hand-built circle
 patterns, the monotone count behind the threshold, and the pinhole
 back-projection."""
