@@ -305,6 +305,22 @@ def extras(cvo, torch, synth, dev, nbatch):
     ex["selected_registration_ms"] = 1e3 * sec
     ex["selected_registration_rot_err_deg"] = float(np.degrees(np.arccos(np.clip((np.trace(R[:3, :3]) - 1) / 2, -1, 1))))
     ex["selected_registration_trans_err_m"] = float(np.linalg.norm(R[:3, 3]))
+    # the paper's pipeline on 8 image frames: select 3k-15k points per frame,
+    # then frame-to-frame registration (first pair 0.95 -> 0.1, then 0.1)
+    s = synth.stereo_images(frames=8)
+    imgs = [tuple(torch.from_numpy(a).to(dev) for a in (f.gray, f.depth, f.feat)) for f in s.frames]
+    first, rest = dict(ell_init=0.95, ell_min=0.1, max_iter=4000), dict(ell_init=0.1, ell_min=0.1, max_iter=4000)
+
+    def pipeline():
+        sel = [cvo.cvo_select_points(*im, s.camera, 15000)[:2] for im in imgs]
+        return cvo.cvo_odometry(sel, s.spec, first, rest)
+
+    sec, (Ts, reps) = timed(pipeline, 1)
+    dt, dr = synth.trajectory_drift(s.poses, list(Ts))
+    ex["selected_odometry_frames"] = len(imgs)
+    ex["selected_odometry_ms"] = 1e3 * sec
+    ex["selected_odometry_drift_pct"] = dt
+    ex["selected_odometry_drift_deg_per_m"] = dr
     return ex
 
 

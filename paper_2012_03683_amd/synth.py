@@ -266,17 +266,21 @@ class Sequence:
         return _inv(self.poses[k]) @ self.poses[k + 1]
 
     def drift(self, rel):
-        """End-point drift of estimated relative poses rel[k] (frame k + 1 in
-        frame k) chained from frame 0, against the true last pose: translation
-        error in % of the path length and rotation error in deg per m."""
-        T = np.eye(4)
-        for R in rel:
-            T = T @ R
-        G = self.poses[len(rel)]
-        E = _inv(G) @ T
-        path = sum(np.linalg.norm(self.relative(k)[:3, 3]) for k in range(len(rel)))
-        ang = np.degrees(np.arccos(np.clip((np.trace(E[:3, :3]) - 1.0) / 2.0, -1.0, 1.0)))
-        return 100.0 * np.linalg.norm(E[:3, 3]) / path, ang / path
+        """End-point drift of estimated relative poses (see trajectory_drift)."""
+        return trajectory_drift(self.poses, rel)
+
+
+def trajectory_drift(poses, rel):
+    """End-point drift of estimated relative poses rel[k] (frame k + 1 in
+    frame k) chained from frame 0, against the true poses: translation error
+    in % of the path length and rotation error in deg per m."""
+    T = np.eye(4)
+    for R in rel:
+        T = T @ R
+    E = _inv(poses[len(rel)]) @ T
+    path = sum(np.linalg.norm((_inv(poses[k]) @ poses[k + 1])[:3, 3]) for k in range(len(rel)))
+    ang = np.degrees(np.arccos(np.clip((np.trace(E[:3, :3]) - 1.0) / 2.0, -1.0, 1.0)))
+    return 100.0 * np.linalg.norm(E[:3, 3]) / path, ang / path
 
 
 def stereo_sequence(seed=1005, frames=8, n=30000, step=1.0, yaw_deg=2.0, semantic=True):
@@ -330,7 +334,8 @@ class ImageSequence:
 def stereo_images(seed=1006, frames=2, step=1.0, yaw_deg=2.0, semantic=True, width=1241, height=376):
     """Full-resolution frames of the stereo-outdoor scene for point selection.
     Camera as in stereo_pair (f = 700, c = (620, 188)); the camera moves `step`
-    m (+-20%) forward and turns `yaw_deg` (+-30%) per frame.  Grey level =
+    m (+-20%) forward and turns `yaw_deg` (+-30%) per frame along a road kept
+    free of boxes (|x| < 3 m).  Grey level =
     255 x surface albedo (U[0.25, 0.9] per plane or box) x (0.55 or 1.0 on a
     0.7 m-wavelength checker pattern of two plane waves in world coordinates)
     + N(0, 1.5), sky 235 + N(0, 1.5), rounded and
@@ -339,6 +344,8 @@ def stereo_images(seed=1006, frames=2, step=1.0, yaw_deg=2.0, semantic=True, wid
     stereo_pair) + 19 Dirichlet(0.3) class probabilities, zero without a hit."""
     rng = np.random.default_rng(seed)
     scene = _stereo_scene(rng)
+    # a clear road: boxes reaching into |x| < 3 m would stand in the camera's path
+    scene.boxes = [b for b in scene.boxes if b[1][0] <= -3.0 or b[0][0] >= 3.0]
     freq, phase = _tex_params(rng, 3.0)
     gfreq, gphase = _tex_params(rng, 0.7)
     albedo = rng.uniform(0.25, 0.9, len(scene.planes) + len(scene.boxes))

@@ -118,3 +118,25 @@ def test_selected_frames_register(cvo):
     print("selected", X.shape[0], Z.shape[0], rep, "error", np.degrees(ang), "deg", tr, "m")
     assert rep["status"] == cvo.CVO_CONVERGED
     assert np.degrees(ang) < 0.5 and tr < 0.1
+
+
+def test_selected_frames_odometry(cvo):
+    """The paper's pipeline on four image frames: select points in each frame,
+    then frame-to-frame registration (the first pair from the identity with
+    ell 0.95 -> 0.1, later pairs warm-started at 0.1); every relative pose
+    lands near the truth and the chained trajectory drifts little."""
+    s = synth.stereo_images(frames=4)
+    sel = []
+    for fr in s.frames:
+        xyz, fo, t = _check(cvo, fr.gray, fr.depth, fr.feat, s.camera, 15000)
+        assert 3000 <= xyz.shape[0] <= 15000
+        sel.append((xyz, fo))
+    Ts, reps = cvo.cvo_odometry(sel, s.spec, dict(ell_init=0.95, ell_min=0.1), dict(ell_init=0.1, ell_min=0.1))
+    for k, T in enumerate(Ts):
+        ang, tr = pose_error(T, s.relative(k))
+        print(k, reps[k]["iterations"], np.degrees(ang), tr)
+        assert reps[k]["status"] == cvo.CVO_CONVERGED
+        assert np.degrees(ang) < 0.2 and tr < 0.03
+    dt, dr = synth.trajectory_drift(s.poses, list(Ts))
+    print("drift", dt, "%", dr, "deg/m")
+    assert dt < 2.0 and dr < 0.1
