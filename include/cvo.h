@@ -232,6 +232,17 @@ cvo_status cvo_align(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,
                      const double T_init[12], double T_out[12], cvo_align_report *report,
                      double *trace);
 
+/* Debugging form of cvo_align: the lengthscale of iteration i is ell_sched[i]
+ * (host array of n > 0 finite values; ap->ell_init, max_iter and fixed_iters
+ * are ignored), with no annealing or convergence decisions, for exactly n
+ * iterations (or until the pair set is empty or the gradient zero).  Fed the
+ * lengthscales another implementation took, it reproduces that run iterate by
+ * iterate.  Other arguments and errors as cvo_align. */
+cvo_status cvo_align_replay(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,
+                            const cvo_feature_spec *spec, const cvo_align_params *ap,
+                            const double T_init[12], const double *ell_sched, int64_t n,
+                            double T_out[12], cvo_align_report *report, double *trace);
+
 /* Hand-written backward of eq. (7) on the pair set frozen at (T, ell): the
  * derivatives of gF * F with respect to the point positions (dX: N x 3,
  * dZ: M x 3), the feature vectors (dU: N x D, dV: M x D) -- all device float32

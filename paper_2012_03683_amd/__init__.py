@@ -30,7 +30,8 @@ CVO_TRACE_LEN = 8
 MAX_BLOCKS = 8
 
 EXPORTS = ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_last_error", "cvo_inner_product",
-           "cvo_gradient", "cvo_evaluate", "cvo_metric", "cvo_cosine", "cvo_align", "cvo_inner_product_backward",
+           "cvo_gradient", "cvo_evaluate", "cvo_metric", "cvo_cosine", "cvo_align", "cvo_align_replay",
+           "cvo_inner_product_backward",
            "cvo_align_batched", "cvo_odometry", "cvo_select_points", "cvo_get_tuning", "cvo_set_tuning", "cvo_autotune",
            "cvo_set_profiling", "cvo_get_timing")
 
@@ -116,6 +117,9 @@ def load_library(path: str = LIB_PATH):
     lib.cvo_cosine.argtypes = common + [P(C.c_double), C.c_void_p]
     lib.cvo_align.argtypes = [H, P(cvo_cloud), P(cvo_cloud), P(cvo_feature_spec), P(cvo_align_params),
                               C.c_void_p, C.c_void_p, P(cvo_align_report), C.c_void_p]
+    lib.cvo_align_replay.argtypes = [H, P(cvo_cloud), P(cvo_cloud), P(cvo_feature_spec), P(cvo_align_params),
+                                     C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, P(cvo_align_report),
+                                     C.c_void_p]
     lib.cvo_inner_product_backward.argtypes = common + [C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
                                                         C.c_void_p, P(C.c_double)]
     lib.cvo_align_batched.argtypes = [H, C.c_int32, P(cvo_cloud), P(cvo_cloud), P(cvo_feature_spec),
@@ -369,6 +373,28 @@ def cvo_align_batched(pairs, spec=None, params=None, T_init=None):
     Ts = np.tile(np.eye(4), (B, 1, 1))
     Ts[:, :3, :] = Tout.reshape(B, 3, 4)
     return Ts, [_report(r) for r in reps]
+
+
+def cvo_align_replay(X, Z, U=None, V=None, spec=None, ell_sched=(), params=None, T_init=None, trace=False):
+    """cvo_align with the lengthscale of iteration i fixed to ell_sched[i]
+    (no annealing decisions, exactly len(ell_sched) iterations); returns
+    (T 4x4, report, trace or None)."""
+    h = handle()
+    cx, cz, keep, sp = _prep(X, Z, U, V, spec)
+    ap, p = _align_params(params)
+    sched = np.ascontiguousarray(np.asarray(ell_sched, dtype=np.float64).reshape(-1))
+    T0 = _pose(np.eye(4) if T_init is None else T_init)
+    Tout = np.zeros(12)
+    rep = cvo_align_report()
+    tr = np.zeros((max(sched.size, 1), CVO_TRACE_LEN)) if trace else None
+    _check(load_library().cvo_align_replay(h, C.byref(cx), C.byref(cz), C.byref(sp), C.byref(ap), T0.ctypes.data,
+                                           sched.ctypes.data if sched.size else None, sched.size, Tout.ctypes.data,
+                                           C.byref(rep), tr.ctypes.data if trace else None), h)
+    del keep
+    T = np.eye(4)
+    T[:3] = Tout.reshape(3, 4)
+    r = _report(rep)
+    return T, r, (tr[:r["iterations"]].copy() if trace else None)
 
 
 def cvo_odometry(frames, spec=None, first=None, rest=None):

@@ -1007,7 +1007,7 @@ template <class F> cvo_status guarded(cvo_context *ctx, F &&f)
 void align_many(cvo_context *ctx, const std::vector<CloudPtrs> &X, const std::vector<CloudPtrs> &Z,
                 const cvo_feature_spec *spec, const std::vector<cvo_align_params> &prm,
                 const std::vector<const double *> &T0, std::vector<PairState> &final_state, double *trace_host,
-                bool use_graph)
+                bool use_graph, const double *d_sched = nullptr, long long n_sched = 0)
 {
     const int B = (int)X.size();
     Problem p;
@@ -1023,6 +1023,8 @@ void align_many(cvo_context *ctx, const std::vector<CloudPtrs> &X, const std::ve
         st[b] = init_state(T0[b], prm[b].ell_init);
         st[b].rc_build = p.kappa * prm[b].ell_init;
         ac[b] = const_for(&prm[b], X[b].n, Z[b].n);
+        ac[b].ell_sched = d_sched;
+        ac[b].n_sched = n_sched;
         ac[b].rebuild_ratio = ctx->tuning.rebuild_ratio;
         ac[b].adaptive = adapt ? 1 : 0;
         class_thresholds(p.lay, ac[b].cls_t);
@@ -1254,6 +1256,41 @@ cvo_status cvo_align(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z, const
         }
         std::vector<PairState> fin;
         align_many(h, {to_ptrs(X)}, {to_ptrs(Z)}, spec, {*ap}, {T_init}, fin, trace, false);
+        std::memcpy(T_out, fin[0].T, sizeof(double) * 12);
+        fill_report(fin[0], report);
+    });
+}
+
+cvo_status cvo_align_replay(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z, const cvo_feature_spec *spec,
+                            const cvo_align_params *ap, const double T_init[12], const double *ell_sched,
+                            int64_t n, double T_out[12], cvo_align_report *report, double *trace)
+{
+    return guarded(h, [&] {
+        check_spec(spec);
+        const int D = spec_dim(spec);
+        check_cloud(X, D, "X");
+        check_cloud(Z, D, "Z");
+        check_align_params(ap);
+        check_pose(T_init);
+        require(T_out != nullptr && report != nullptr, "T_out / report is NULL");
+        require(ell_sched != nullptr && n >= 1, "the schedule needs at least one lengthscale");
+        for (int64_t i = 0; i < n; ++i)
+            require(std::isfinite(ell_sched[i]) && ell_sched[i] > 0.0, "schedule lengthscales must be finite and > 0");
+        cvo_align_params rp = *ap;
+        rp.ell_init = ell_sched[0];
+        rp.max_iter = n;
+        rp.fixed_iters = 0;
+        if (X->n == 0 || Z->n == 0) {
+            std::memcpy(T_out, T_init, sizeof(double) * 12);
+            PairState s = init_state(T_init, rp.ell_init);
+            s.status = ST_NO_OVERLAP;
+            fill_report(s, report);
+            return;
+        }
+        double *d_sched = h->get_t<double>("replay.ell", (size_t)n);
+        h->upload(d_sched, ell_sched, sizeof(double) * (size_t)n);
+        std::vector<PairState> fin;
+        align_many(h, {to_ptrs(X)}, {to_ptrs(Z)}, spec, {rp}, {T_init}, fin, trace, false, d_sched, n);
         std::memcpy(T_out, fin[0].T, sizeof(double) * 12);
         fill_report(fin[0], report);
     });

@@ -71,6 +71,8 @@ struct alignas(16) AlignConst {
     int metric;          // 0: kinetic-energy metric of the moving cloud, 1: identity
     int adaptive;        // nonzero: also pause when the density class drops below cls_built
     double cls_t[3];     // pairs per query where density classes 3, 2 and 1 begin
+    const double *ell_sched;  // replay: lengthscale of every iteration (device; null: annealing)
+    long long n_sched;        // replay: iterations to run
 };
 
 // Uniform grid of one cloud (reference role).

@@ -238,7 +238,15 @@ __device__ __forceinline__ void finalize_local(PairState &st, const AlignConst &
     }
     st.it = it + 1;
     st.total_pairs += np;
-    if (!ac.fixed_iters) {
+    if (ac.ell_sched) {
+        // replay of a given lengthscale sequence: no annealing or convergence decisions
+        if (it + 1 >= ac.n_sched) {
+            st.status = ST_MAX_ITER;
+            st.done = 1;
+            return;
+        }
+        st.ell = ac.ell_sched[it + 1];
+    } else if (!ac.fixed_iters) {
         const double ip = st.i_prev;
         if (isfinite(ip) && fabs(ind - ip) <= ac.ind_rel_tol * fabs(ind) && ell > ac.ell_min) {
             const double e2 = ac.decay * ell;

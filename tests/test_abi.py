@@ -19,7 +19,7 @@ def declared():
 
 def test_header_declares_the_entry_points():
     names = declared()
-    for must in ("cvo_inner_product", "cvo_gradient", "cvo_align", "cvo_metric", "cvo_cosine", "cvo_odometry", "cvo_select_points",
+    for must in ("cvo_inner_product", "cvo_gradient", "cvo_align", "cvo_metric", "cvo_cosine", "cvo_odometry", "cvo_select_points", "cvo_align_replay",
                  "cvo_inner_product_backward", "cvo_align_batched", "cvo_create", "cvo_destroy"):
         assert must in names
 

@@ -161,3 +161,34 @@ def test_full_size_evaluation_at_truth_and_identity(cvo, which):
             print(which, ell, "|P|", g["n_pairs"])
             assert_eval_matches(g, o, what=f"{which} ell={ell}")
             assert g["curv"] == pytest.approx(o["phi2"], rel=1e-4)
+
+
+@pytest.mark.parametrize("kind", ["stereo", "rgbd"])
+def test_annealed_run_replayed_iterate_by_iterate(cvo, kind):
+    """The oracle's annealed run replayed on the GPU with the oracle's own
+    lengthscale at every iteration (cvo_align_replay): the iterates are
+    compared one by one -- F within 1e-5 (every term is positive, so |F| is
+    its absolute sum), |P| exact except at a rare pair sitting on the cutoff
+    where the two poses differ by rounding, and the final pose within
+    1e-4 rad / 1e-4 m."""
+    if kind == "stereo":
+        p = synth.stereo_pair(seed=1001, n=2500)
+        prm = dict(p.align, ell_init=0.95, ell_min=0.2, max_iter=1500)
+    else:
+        p = synth.rgbd_pair(seed=1002, n=3000)
+        prm = dict(p.align, ell_init=0.1, ell_min=0.05, max_iter=1500)
+    X, Z, U, V = to_dev(p, torch)
+    To, ro, tro = oracle.align(p.x, p.u, p.z, p.v, p.spec, prm)
+    sched = tro[:, 1].copy()
+    Tg, rg, trg = cvo.cvo_align_replay(X, Z, U, V, p.spec, sched, prm, trace=True)
+    print(kind, "iterations", len(sched), rg)
+    assert rg["iterations"] == len(sched) and rg["status"] == cvo.CVO_MAX_ITER
+    np.testing.assert_array_equal(trg[:, 1], sched)
+    np.testing.assert_allclose(trg[:, 2], tro[:, 2], rtol=1e-5)
+    differ = np.flatnonzero(trg[:, 6] != tro[:, 6])
+    print(kind, "iterations with a different |P|:", differ.size)
+    assert differ.size <= max(1, len(sched) // 100)
+    np.testing.assert_allclose(trg[:, 6], tro[:, 6], rtol=1e-5)
+    ang, tr = pose_error(Tg, To)
+    print(kind, "final pose deviation", ang, tr)
+    assert ang < 1e-4 and tr < 1e-4
