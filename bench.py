@@ -95,7 +95,7 @@ def main():
                     help="only run a plain 256 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "the library runs on one GPU; more than one is not supported (use --gpus 1)"}))
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
