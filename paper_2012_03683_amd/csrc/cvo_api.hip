@@ -359,9 +359,20 @@ int bits_for(unsigned long long v)
 }
 
 // bounding boxes and the non-finite check
+// Bounding boxes of one call's clouds, kept for the views rebuilt later in
+// the same call (the clouds cannot change while a call runs).
+struct BoxCache {
+    std::vector<float> box;
+    CloudPtrs *dc = nullptr;
+};
+
 std::vector<float> cloud_boxes(cvo_context *ctx, const std::string &pre, const std::vector<CloudPtrs> &cl,
-                               CloudPtrs **d_clouds)
+                               CloudPtrs **d_clouds, BoxCache *cache = nullptr)
 {
+    if (cache && cache->dc) {
+        *d_clouds = cache->dc;
+        return cache->box;
+    }
     const int B = (int)cl.size();
     CloudPtrs *dc = ctx->get_t<CloudPtrs>(pre + ".clouds", B);
     ctx->upload(dc, cl.data(), sizeof(CloudPtrs) * B);
@@ -373,6 +384,10 @@ std::vector<float> cloud_boxes(cvo_context *ctx, const std::string &pre, const s
     for (int c = 0; c < B; ++c)
         require(box[8 * c + 6] == 0.0f, "a cloud has non-finite coordinates");
     *d_clouds = dc;
+    if (cache) {
+        cache->box = box;
+        cache->dc = dc;
+    }
     return box;
 }
 
@@ -424,14 +439,15 @@ ViewShape density_shape(const cvo_context *ctx, int cls, const FeatLayout &lay)
 }
 
 GridView build_grid(cvo_context *ctx, const std::string &pre, const std::vector<CloudPtrs> &cl,
-                    const std::vector<double> &rc, const FeatLayout &lay, const std::vector<ViewShape> &shape)
+                    const std::vector<double> &rc, const FeatLayout &lay, const std::vector<ViewShape> &shape,
+                    BoxCache *bc = nullptr)
 {
     GridView v;
     const int B = (int)cl.size();
     v.B = B;
     v.rc = rc;
     CloudPtrs *dc = nullptr;
-    std::vector<float> box = cloud_boxes(ctx, pre, cl, &dc);
+    std::vector<float> box = cloud_boxes(ctx, pre, cl, &dc, bc);
     const long long cell_cap = 1LL << 23;
     v.desc.resize(B);
     long long cell_base = 0, pt_base = 0, max_cells = 0, nmax = 0;
@@ -518,14 +534,15 @@ GridView build_grid(cvo_context *ctx, const std::string &pre, const std::vector<
 }
 
 ClusterView build_clusters(cvo_context *ctx, const std::string &pre, const std::vector<CloudPtrs> &cl,
-                           const std::vector<double> &rc, const FeatLayout &lay, const std::vector<ViewShape> &shape)
+                           const std::vector<double> &rc, const FeatLayout &lay, const std::vector<ViewShape> &shape,
+                           BoxCache *bc = nullptr)
 {
     ClusterView v;
     const int B = (int)cl.size();
     v.B = B;
     v.rc = rc;
     CloudPtrs *dc = nullptr;
-    std::vector<float> box = cloud_boxes(ctx, pre, cl, &dc);
+    std::vector<float> box = cloud_boxes(ctx, pre, cl, &dc, bc);
     const int cbits = bits_for((unsigned long long)(B > 1 ? B - 1 : 0));
     const int maxbits = std::min(19, (62 - cbits) / 3);
     std::vector<ClusterBuild> cb(B);
@@ -813,6 +830,7 @@ struct Problem {
     int nblk = 1;
     double kappa = 3.0;
     float sig2 = 1.f;
+    BoxCache box_x, box_z;  // bounding boxes from the first view build
 };
 
 // Grid of X, clusters of Z, and the work plan at the pose held in the device
@@ -823,8 +841,8 @@ void build_views(cvo_context *ctx, Problem &p, const std::vector<CloudPtrs> &X, 
     p.shape = shape;
     std::vector<double> rc(ell.size());
     for (size_t k = 0; k < ell.size(); ++k) rc[k] = p.kappa * ell[k];
-    p.grid = build_grid(ctx, "fx", X, rc, p.lay, shape);
-    p.clus = build_clusters(ctx, "fz", Z, rc, p.lay, shape);
+    p.grid = build_grid(ctx, "fx", X, rc, p.lay, shape, &p.box_x);
+    p.clus = build_clusters(ctx, "fz", Z, rc, p.lay, shape, &p.box_z);
     p.plan = make_plan(ctx, "fp", p.clus, p.grid, p.d_state, 0, p.kappa);
     p.mom = moments(ctx, "fm", p.plan.nslots, p.lay.d4, false);
     p.nblk = reduce_blocks(p.clus.desc);
