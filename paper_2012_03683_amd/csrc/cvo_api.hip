@@ -651,8 +651,10 @@ struct Plan {
     long long nslots = 0;
 };
 
+// With exact_slots false, nslots is only an upper bound (64 queries per
+// piece), which sizes the forward moments without a host read.
 Plan make_plan(cvo_context *ctx, const std::string &pre, const ClusterView &q, const GridView &r,
-               const PairState *d_state, int inverse, double kappa)
+               const PairState *d_state, int inverse, double kappa, bool exact_slots = true)
 {
     Plan pl;
     if (q.nclus == 0) return pl;
@@ -702,9 +704,13 @@ Plan make_plan(cvo_context *ctx, const std::string &pre, const ClusterView &q, c
     pl.recs = ctx->get_t<PieceRec>(pre + ".recs", std::max(P, 1));
     launch_plan_records(pl.porder, pl.pieces, q.cpair, q.clus, q.cgeo, P, pl.recs, ctx->stream);
     ctx->check_launch("plan emit");
-    int nslots = 0;
-    ctx->download(&nslots, d_total + 1, sizeof(int));
-    pl.nslots = nslots;
+    if (exact_slots) {
+        int nslots = 0;
+        ctx->download(&nslots, d_total + 1, sizeof(int));
+        pl.nslots = nslots;
+    } else {
+        pl.nslots = (long long)P * kWave;
+    }
     return pl;
 }
 
@@ -843,7 +849,7 @@ void build_views(cvo_context *ctx, Problem &p, const std::vector<CloudPtrs> &X, 
     for (size_t k = 0; k < ell.size(); ++k) rc[k] = p.kappa * ell[k];
     p.grid = build_grid(ctx, "fx", X, rc, p.lay, shape, &p.box_x);
     p.clus = build_clusters(ctx, "fz", Z, rc, p.lay, shape, &p.box_z);
-    p.plan = make_plan(ctx, "fp", p.clus, p.grid, p.d_state, 0, p.kappa);
+    p.plan = make_plan(ctx, "fp", p.clus, p.grid, p.d_state, 0, p.kappa, false);
     p.mom = moments(ctx, "fm", p.plan.nslots, p.lay.d4, false);
     p.nblk = reduce_blocks(p.clus.desc);
     p.partials = ctx->get_t<double>("partials", shape.size() * (size_t)p.nblk * kRedVals);
