@@ -192,3 +192,23 @@ def test_annealed_run_replayed_iterate_by_iterate(cvo, kind):
     ang, tr = pose_error(Tg, To)
     print(kind, "final pose deviation", ang, tr)
     assert ang < 1e-4 and tr < 1e-4
+
+
+def test_align_replay_edge_cases(cvo):
+    """Replay rejects an empty schedule and non-positive lengthscales, runs
+    exactly the given number of iterations at the given lengthscales, and an
+    empty cloud reports NO_OVERLAP with the start pose."""
+    p = synth.tiny_cube(seed=9, n=400)
+    X, Z, U, V = to_dev(p, torch)
+    with pytest.raises(cvo.CvoError):
+        cvo.cvo_align_replay(X, Z, U, V, p.spec, [], p.align)
+    with pytest.raises(cvo.CvoError):
+        cvo.cvo_align_replay(X, Z, U, V, p.spec, [0.1, -0.1], p.align)
+    sched = [0.3, 0.3, 0.2, 0.2, 0.15]
+    T, r, tr = cvo.cvo_align_replay(X, Z, U, V, p.spec, sched, p.align, trace=True)
+    assert r["iterations"] == 5 and r["status"] == cvo.CVO_MAX_ITER
+    np.testing.assert_array_equal(tr[:, 1], sched)
+    T0 = p.T_gt
+    T, r, _ = cvo.cvo_align_replay(X[:0], Z, U[:0], V, p.spec, sched, p.align, T_init=T0)
+    assert r["status"] == cvo.CVO_NO_OVERLAP
+    np.testing.assert_array_equal(T, T0)
