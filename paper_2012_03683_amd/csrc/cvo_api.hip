@@ -162,8 +162,11 @@ struct cvo_context {
             ev_free.pop_back();
             return e;
         }
+        // timing only: no system-scope fence (cache write-back and invalidate)
+        // when the event is recorded, so the events neither slow nor pad the
+        // kernels they bracket; their times are read after a stream wait
         hipEvent_t e;
-        HIP_OK(hipEventCreate(&e));
+        HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
         return e;
     }
     void harvest_events()
