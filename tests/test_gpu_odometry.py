@@ -89,3 +89,23 @@ def test_odometry_edge_cases(cvo):
     np.testing.assert_array_equal(Tg, np.tile(np.eye(4), (2, 1, 1)))
     with pytest.raises(cvo.CvoError):
         cvo.cvo_odometry(fr[:1], s.spec, s.first, s.rest)
+
+
+def test_geometric_odometry_matches_oracle(cvo):
+    """Geometric CVO (no feature blocks, c_ij = 1, eq. (8)) over three frames
+    of 1500 points: every relative pose within 1e-4 rad / 1e-4 m of the
+    oracle's."""
+    s = synth.stereo_sequence(frames=3, n=1500, semantic=False)
+    frames = [(x, None) for x, _ in s.frames]
+    d = torch.device("cuda:0")
+    fr = [(torch.from_numpy(x).to(d), None) for x, _ in frames]
+    first = dict(s.first, ell_min=0.25, max_iter=1500)
+    rest = dict(s.rest, ell_init=0.25, ell_min=0.25, max_iter=1500)
+    Tg, rg = cvo.cvo_odometry(fr, [], first, rest)
+    To, ro = oracle.odometry(frames, [], first, rest)
+    for k in range(2):
+        print(k, rg[k], ro[k])
+        assert rg[k]["status"] == ro[k]["status"] == oracle.CONVERGED
+        ang, tr = pose_error(Tg[k], To[k])
+        print(k, "pose deviation", ang, tr)
+        assert ang < 1e-4 and tr < 1e-4
