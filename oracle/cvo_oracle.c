@@ -485,6 +485,7 @@ static void compose_left(const double B[12], double A[12])
  * Per iteration, at the current (T, ell):
  *   a. evaluate F, the gradient g = (omega, v) and |P|.
  *      |P| = 0 -> NO_OVERLAP; g = 0 -> STATIONARY (no step).
+ *      A metric G that cannot be solved also ends as STATIONARY (no step).
  *   b. indicator i = F / sqrt(|X||Z|)                         (eq. (10))
  *   c. ascent direction d = G^-1 g, the Riemannian gradient for the metric G
  *      (kinetic-energy metric of the moving cloud, or the identity), and the
@@ -543,7 +544,9 @@ int oracle_align(const oracle_cloud *X, const oracle_cloud *Z, const oracle_spec
         if (ap->metric == ORACLE_METRIC_KINETIC) {
             double G[36];
             oracle_metric_tensor(T, Z->xyz, M, G);
-            if (oracle_solve6(G, g, d)) { free(zt); return -3; }
+            /* no direction solves G d = g: nothing defines an ascent step, so
+             * the iterate is taken as stationary (no step is made) */
+            if (oracle_solve6(G, g, d)) { status = ORACLE_STATIONARY; break; }
         } else {
             for (int k = 0; k < 6; ++k) d[k] = g[k];
         }
