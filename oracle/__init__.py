@@ -28,6 +28,7 @@ _SRC = os.path.join(_HERE, "cvo_oracle.c")
 SE, LIN = 0, 1
 CONVERGED, MAX_ITER, NO_OVERLAP, STATIONARY = 1, 2, 3, 4
 METRIC_KINETIC, METRIC_IDENTITY = 0, 1
+ELL_ANNEAL, ELL_ADAPTIVE = 0, 1
 EVAL_LEN, TRACE_LEN, REPORT_LEN = 18, 8, 6
 MAX_BLOCKS = 8
 
@@ -56,7 +57,8 @@ class _AlignParams(C.Structure):
     _fields_ = [("ell_init", C.c_double), ("ell_min", C.c_double), ("decay", C.c_double),
                 ("ind_rel_tol", C.c_double), ("eps_rot", C.c_double), ("eps_trans", C.c_double),
                 ("step_lambda", C.c_double), ("sigma", C.c_double), ("kappa", C.c_double),
-                ("max_iter", C.c_int64), ("fixed_iters", C.c_int32), ("metric", C.c_int32)]
+                ("max_iter", C.c_int64), ("fixed_iters", C.c_int32), ("metric", C.c_int32),
+                ("ell_mode", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -76,6 +78,8 @@ def _load():
                                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         lib.oracle_evaluate_dir.argtypes = [P(_Cloud), P(_Cloud), P(_Spec), C.c_double, C.c_double,
                                             C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, P(C.c_int64)]
+        lib.oracle_ell_objective.argtypes = [P(_Cloud), P(_Cloud), P(_Spec), C.c_double, C.c_double,
+                                             C.c_double, C.c_void_p, C.c_void_p]
         lib.oracle_metric_tensor.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
         lib.oracle_metric_tensor.restype = None
         lib.oracle_solve6.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
@@ -212,7 +216,23 @@ def transform(T, z):
 
 DEFAULT_ALIGN = dict(ell_init=0.1, ell_min=0.1, decay=0.98, ind_rel_tol=1e-3, eps_rot=1e-6,
                      eps_trans=1e-6, step_lambda=1.0, sigma=1.0, kappa=3.0, max_iter=4000,
-                     fixed_iters=False, metric=METRIC_KINETIC)
+                     fixed_iters=False, metric=METRIC_KINETIC, ell_mode=ELL_ANNEAL)
+
+
+def ell_objective(x, u, z, v, spec, ell, T=None, sigma=1.0, kappa=3.0):
+    """The lengthscale objective of the adaptive mode (Sec. VI): J(T, ell) =
+    sum_{W_j > 0} log W_j - 3 |Z+| log ell on the pair set frozen at (T, ell),
+    its ell-derivative, the maximum-likelihood lengthscale
+    sqrt(sum_j r_j / (3 |Z+|)) (r_j = target j's weighted mean squared
+    residual) and |Z+|."""
+    p = _Pair(x, u, z, v, spec)
+    T = _pose(np.eye(4) if T is None else T)
+    out = np.zeros(4)
+    rc = _load().oracle_ell_objective(C.byref(p.X), C.byref(p.Z), C.byref(p.S), ell, sigma, kappa,
+                                      T.ctypes.data, out.ctypes.data)
+    if rc:
+        raise ValueError(f"oracle_ell_objective failed ({rc})")
+    return {"J": out[0], "dJ_dell": out[1], "ell_ml": out[2], "n_plus": int(out[3])}
 
 
 def metric_tensor(T, z):
@@ -241,7 +261,7 @@ def align(x, u, z, v, spec, params=None, T_init=None, trace=True):
     ap = _AlignParams(prm["ell_init"], prm["ell_min"], prm["decay"], prm["ind_rel_tol"],
                       prm["eps_rot"], prm["eps_trans"], prm["step_lambda"], prm["sigma"],
                       prm["kappa"], int(prm["max_iter"]), int(bool(prm["fixed_iters"])),
-                      int(prm["metric"]))
+                      int(prm["metric"]), int(prm["ell_mode"]), 0)
     T0 = _pose(np.eye(4) if T_init is None else T_init)
     Tout = np.zeros(12)
     rep = np.zeros(REPORT_LEN)

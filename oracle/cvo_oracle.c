@@ -364,6 +364,77 @@ int oracle_target_moments(const oracle_cloud *X, const oracle_cloud *Z, const or
 }
 
 /* ------------------------------------------------------------------ */
+/* The lengthscale as an optimisation variable (Sec. VI names Adaptive CVO,
+ * which makes the lengthscale part of what is optimised, without a formula).
+ * F of eq. (7) grows with ell, so F itself cannot choose it.  Reading: ell
+ * maximises the log-likelihood of the moved cloud under the kernel mixture
+ * centred on X, the kernel of eq. (2) normalised as a density over R^3:
+ *   J(T, ell) = sum_{j in Z+} log W_j(T, ell) - 3 |Z+| log ell,
+ *   W_j = sum_{i : (i,j) in P} w_ij,   Z+ = {j : W_j > 0},
+ * on the pair set frozen at (T, ell), as for dF/dell.  With
+ *   r_j = (sum_i w_ij s_ij) / W_j   (target j's weighted mean squared residual)
+ *   dJ/dell = sum_{j in Z+} r_j / ell^3 - 3 |Z+| / ell,
+ * which is zero at ell^2 = sum_{j in Z+} r_j / (3 |Z+|) when the r_j are held
+ * fixed (the variance update of EM for a Gaussian mixture).
+ * zt: the moved targets (3 M doubles).  out as ORACLE_ELLOBJ_LEN.        */
+static int ell_objective_zt(const oracle_cloud *X, const oracle_cloud *Z, const oracle_spec *sp, double ell,
+                            double sigma, double kappa, const double *zt, double out[ORACLE_ELLOBJ_LEN])
+{
+    const int D = spec_dim(sp);
+    const int64_t N = X->n, M = Z->n;
+    const double rc2 = cutoff_sq(ell, kappa);
+    const double s2 = sigma * sigma;
+    double *Wj = (double *)calloc((size_t)(M > 0 ? M : 1), sizeof(double));
+    double *Ws = (double *)calloc((size_t)(M > 0 ? M : 1), sizeof(double));
+    if (!Wj || !Ws) { free(Wj); free(Ws); return -2; }
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < M; ++j) {
+        const float *vj = D ? Z->feat + (size_t)D * j : NULL;
+        double w_ = 0.0, ws_ = 0.0;
+        for (int64_t i = 0; i < N; ++i) {
+            double d[3];
+            const double s = canonical_distance(X->xyz + 3 * i, zt + 3 * j, d);
+            if (!(s <= rc2)) continue;
+            const float *ui = D ? X->feat + (size_t)D * i : NULL;
+            const double w = feature_kernel(sp, ui, vj, NULL) * (s2 * exp(-s / (2.0 * ell * ell)));
+            w_ += w;
+            ws_ += w * s;
+        }
+        Wj[j] = w_;
+        Ws[j] = ws_;
+    }
+    double J = 0.0, rsum = 0.0;
+    int64_t mp = 0;
+    for (int64_t j = 0; j < M; ++j) {
+        if (!(Wj[j] > 0.0)) continue;
+        J += log(Wj[j]);
+        rsum += Ws[j] / Wj[j];
+        mp += 1;
+    }
+    free(Wj);
+    free(Ws);
+    out[ORACLE_J] = J - 3.0 * (double)mp * log(ell);
+    out[ORACLE_DJ] = rsum / (ell * ell * ell) - 3.0 * (double)mp / ell;
+    out[ORACLE_ELL_ML] = mp > 0 ? sqrt(rsum / (3.0 * (double)mp)) : 0.0;
+    out[ORACLE_ZPLUS] = (double)mp;
+    return 0;
+}
+
+int oracle_ell_objective(const oracle_cloud *X, const oracle_cloud *Z, const oracle_spec *sp,
+                         double ell, double sigma, double kappa, const double T[12],
+                         double out[ORACLE_ELLOBJ_LEN])
+{
+    if (!(ell > 0.0) || !(sigma > 0.0) || !(kappa > 0.0)) return -1;
+    const int64_t M = Z->n;
+    double *zt = (double *)malloc(sizeof(double) * 3 * (M > 0 ? M : 1));
+    if (!zt) return -2;
+    oracle_transform(T, Z->xyz, M, zt);
+    const int rc = ell_objective_zt(X, Z, sp, ell, sigma, kappa, zt, out);
+    free(zt);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
 /* Metric on se(3) used for the ascent direction: the kinetic energy of the
  * moving cloud as a rigid body with unit masses,
  *   xi^T G xi = (1/M) sum_j |omega x z'_j + v|^2,  G = (1/M) sum_j J_j^T J_j,
@@ -501,6 +572,13 @@ static void compose_left(const double B[12], double A[12])
  *      (eps_rot, eps_trans).
  *   g. stop at max_iter.
  * In fixed-iteration mode e. and f. are skipped.
+ * Adaptive mode (ell_mode = ORACLE_ELL_ADAPTIVE) replaces e. and f.:
+ *   e'. ell <- ell_ml of oracle_ell_objective at the iteration's (T, ell)
+ *       (before the step), kept within [ell_min, ell_init] and within a
+ *       factor `decay` of ell (at most one annealing decay per iteration,
+ *       down or up); unchanged when Z+ is empty.
+ *   f'. converged when the step moved less than (eps_rot, eps_trans) and
+ *       ell changed by at most ind_rel_tol * ell.
  * trace (may be NULL): per iteration ORACLE_TRACE_LEN doubles.          */
 int oracle_align(const oracle_cloud *X, const oracle_cloud *Z, const oracle_spec *sp,
                  const oracle_align_params *ap, const double T_init[12], double T_out[12],
@@ -552,6 +630,14 @@ int oracle_align(const oracle_cloud *X, const oracle_cloud *Z, const oracle_spec
         }
         const double slope = dot3(g, d) + dot3(g + 3, d + 3);
         const double phi2 = eval_curvature(X, Z, sp, ell, ap->sigma, ap->kappa, zt, d);
+        double ell_ml = 0.0;
+        const int adaptive = ap->ell_mode == ORACLE_ELL_ADAPTIVE && !ap->fixed_iters;
+        if (adaptive) {
+            double eo[ORACLE_ELLOBJ_LEN];
+            rc = ell_objective_zt(X, Z, sp, ell, ap->sigma, ap->kappa, zt, eo);
+            if (rc) { free(zt); return rc; }
+            ell_ml = eo[ORACLE_ELL_ML];
+        }
         const double tauN = (phi2 < 0.0) ? slope / (-phi2) : INFINITY;
         const double nw = sqrt(dot3(d, d)), nv = sqrt(dot3(d + 3, d + 3));
         const double tauC = ap->step_lambda * ell / (nw * p.rmax + nv);
@@ -572,7 +658,21 @@ int oracle_align(const oracle_cloud *X, const oracle_cloud *Z, const oracle_spec
             tr[7] = phi2;
         }
         it += 1;
-        if (!ap->fixed_iters) {
+        if (adaptive) {
+            double next = ell;
+            if (ell_ml > 0.0) {
+                double lo = ap->decay * ell, hi = ell / ap->decay;
+                if (lo < ap->ell_min) lo = ap->ell_min;
+                if (hi > ap->ell_init) hi = ap->ell_init;
+                next = ell_ml < lo ? lo : (ell_ml > hi ? hi : ell_ml);
+            }
+            const int still = fabs(next - ell) <= ap->ind_rel_tol * ell;
+            ell = next;
+            if (still && tau * nw < ap->eps_rot && tau * nv < ap->eps_trans) {
+                status = ORACLE_CONVERGED;
+                break;
+            }
+        } else if (!ap->fixed_iters) {
             if (isfinite(i_prev) && fabs(ind - i_prev) <= ap->ind_rel_tol * fabs(ind) &&
                 ell > ap->ell_min) {
                 double e2 = ap->decay * ell;

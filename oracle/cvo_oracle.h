@@ -48,6 +48,17 @@ typedef struct {
     double sigma[ORACLE_MAX_BLOCKS];
 } oracle_spec;
 
+/* how the lengthscale moves during a registration */
+#define ORACLE_ELL_ANNEAL 0   /* Sec. IV: decay by `decay` when the indicator stabilises */
+#define ORACLE_ELL_ADAPTIVE 1 /* Sec. VI: ell follows the maximiser of oracle_ell_objective's J */
+
+/* layout of oracle_ell_objective's output vector */
+#define ORACLE_J 0        /* J(T, ell) */
+#define ORACLE_DJ 1       /* dJ/dell, pair set frozen */
+#define ORACLE_ELL_ML 2   /* sqrt(sum_j r_j / (3 |Z+|)), 0 when Z+ is empty */
+#define ORACLE_ZPLUS 3    /* |Z+| */
+#define ORACLE_ELLOBJ_LEN 4
+
 typedef struct {
     double ell_init, ell_min, decay, ind_rel_tol;
     double eps_rot, eps_trans, step_lambda;
@@ -55,6 +66,8 @@ typedef struct {
     int64_t max_iter;
     int32_t fixed_iters;
     int32_t metric;
+    int32_t ell_mode;  /* ORACLE_ELL_ANNEAL or ORACLE_ELL_ADAPTIVE */
+    int32_t reserved;
 } oracle_align_params;
 
 int oracle_num_threads(void);
@@ -72,6 +85,9 @@ int oracle_target_moments(const oracle_cloud *X, const oracle_cloud *Z, const or
                           const int64_t *idx, int64_t nidx, double *W, double *D, double *S,
                           int64_t *cnt);
 void oracle_exp_se3(const double xi[6], double T[12]);
+int oracle_ell_objective(const oracle_cloud *X, const oracle_cloud *Z, const oracle_spec *sp,
+                         double ell, double sigma, double kappa, const double T[12],
+                         double out[ORACLE_ELLOBJ_LEN]);
 int oracle_align(const oracle_cloud *X, const oracle_cloud *Z, const oracle_spec *sp,
                  const oracle_align_params *ap, const double T_init[12], double T_out[12],
                  double report[ORACLE_REPORT_LEN], double *trace);
