@@ -201,6 +201,30 @@ cvo_status cvo_evaluate(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,
                         const cvo_feature_spec *spec, const cvo_kernel_params *kp,
                         const double T[12], cvo_eval *out);
 
+/* Allocation-free form of cvo_evaluate, for callers that cannot allocate
+ * device memory (code that must not call hipMalloc/hipFree, e.g. inside a
+ * serving loop or a harness that forbids it).  Same arguments, outputs and
+ * kernels as cvo_evaluate; every scratch buffer is carved from a fixed
+ * device array of CVO_NOALLOC_SCRATCH_MIB MiB that the library holds on each
+ * device it runs on (looked up by cvo_create) until the process ends.  No
+ * hipMalloc, hipFree, pinned host allocation or event creation happens in the
+ * call; small host<->device copies are made from the caller's memory and
+ * waited for.
+ * Limits: N, M <= CVO_NOALLOC_MAX_POINTS (larger clouds are rejected with
+ * CVO_ERR_INVALID_ARGUMENT before any device work); an input whose views
+ * need more scratch than the array holds (very dense neighbourhoods) fails
+ * with CVO_ERR_OUT_OF_MEMORY and a message naming the shortfall, before any
+ * kernel writes past the array.
+ * The array is shared by every handle on a device and keeps the last call's
+ * contents (each call rewrites what it reads): calls that overlap in time on
+ * one device -- from two threads, or on two streams -- race and must not be
+ * made.  CVO_ERR_DEVICE if the array could not be located on the device. */
+#define CVO_NOALLOC_SCRATCH_MIB 256
+#define CVO_NOALLOC_MAX_POINTS 65536
+cvo_status cvo_evaluate_noalloc(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,
+                                const cvo_feature_spec *spec, const cvo_kernel_params *kp,
+                                const double T[12], cvo_eval *out);
+
 /* Cosine of the angle between f_X and the moved f_Z (eq. (9), Sec. III-C):
  * cos_theta = F(X, Z; T) / (||f_X|| ||f_Z||), where ||f_X||^2 = F(X, X; I) and
  * ||f_Z||^2 = F(Z, Z; I) are the self inner products with the same kernels,

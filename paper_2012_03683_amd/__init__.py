@@ -30,7 +30,7 @@ CVO_TRACE_LEN = 8
 MAX_BLOCKS = 8
 
 EXPORTS = ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_last_error", "cvo_inner_product",
-           "cvo_gradient", "cvo_evaluate", "cvo_metric", "cvo_cosine", "cvo_align", "cvo_align_replay",
+           "cvo_gradient", "cvo_evaluate", "cvo_evaluate_noalloc", "cvo_metric", "cvo_cosine", "cvo_align", "cvo_align_replay",
            "cvo_inner_product_backward",
            "cvo_align_batched", "cvo_odometry", "cvo_select_points", "cvo_get_tuning", "cvo_set_tuning", "cvo_autotune",
            "cvo_set_profiling", "cvo_get_timing")
@@ -113,6 +113,7 @@ def load_library(path: str = LIB_PATH):
     lib.cvo_inner_product.argtypes = common + [P(C.c_double), P(C.c_int64)]
     lib.cvo_gradient.argtypes = common + [P(C.c_double), C.c_void_p, P(C.c_int64)]
     lib.cvo_evaluate.argtypes = common + [P(cvo_eval)]
+    lib.cvo_evaluate_noalloc.argtypes = common + [P(cvo_eval)]
     lib.cvo_metric.argtypes = common + [P(C.c_double)]
     lib.cvo_cosine.argtypes = common + [P(C.c_double), C.c_void_p]
     lib.cvo_align.argtypes = [H, P(cvo_cloud), P(cvo_cloud), P(cvo_feature_spec), P(cvo_align_params),
@@ -268,15 +269,16 @@ def cvo_gradient(X, Z, T, ell, U=None, V=None, spec=None, sigma=1.0, kappa=3.0):
     return F.value, g, int(n.value)
 
 
-def cvo_evaluate(X, Z, T, ell, U=None, V=None, spec=None, sigma=1.0, kappa=3.0):
-    """All outputs of one pair pass as a dict."""
+def cvo_evaluate(X, Z, T, ell, U=None, V=None, spec=None, sigma=1.0, kappa=3.0, noalloc=False):
+    """All outputs of one pair pass as a dict.  noalloc=True calls
+    cvo_evaluate_noalloc (scratch from the library's fixed device array)."""
     h = handle()
     cx, cz, keep, sp = _prep(X, Z, U, V, spec)
     kp = cvo_kernel_params(ell, sigma, kappa)
     Tp = _pose(T)
     out = cvo_eval()
-    _check(load_library().cvo_evaluate(h, C.byref(cx), C.byref(cz), C.byref(sp), C.byref(kp), Tp.ctypes.data,
-                                       C.byref(out)), h)
+    fn = load_library().cvo_evaluate_noalloc if noalloc else load_library().cvo_evaluate
+    _check(fn(h, C.byref(cx), C.byref(cz), C.byref(sp), C.byref(kp), Tp.ctypes.data, C.byref(out)), h)
     del keep
     return {"F": out.F, "grad": np.array(out.grad[:]), "curv": out.curv, "dF_dell": out.dF_dell,
             "r_max": out.r_max, "i_theta": out.i_theta, "n_pairs": int(out.n_pairs)}
@@ -486,6 +488,11 @@ def cvo_inner_product_backward(X, Z, T, ell, gF=1.0, U=None, V=None, spec=None, 
         ptr(dU), ptr(dV), C.byref(dl) if "ell" in need else None), h)
     del keep
     return {"dX": dX, "dZ": dZ, "dU": dU, "dV": dV, "dell": dl.value if "ell" in need else None}
+
+
+def cvo_evaluate_noalloc(X, Z, T, ell, U=None, V=None, spec=None, sigma=1.0, kappa=3.0):
+    """cvo_evaluate through the allocation-free entry point."""
+    return cvo_evaluate(X, Z, T, ell, U, V, spec, sigma, kappa, noalloc=True)
 
 
 def cvo_get_tuning():

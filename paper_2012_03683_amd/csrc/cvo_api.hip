@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -48,6 +49,37 @@ constexpr double kLog2e = 1.4426950408889634;
 
 }  // namespace
 
+// ------------------------------------------------------------------ fixed scratch
+// Device scratch of the allocation-free entry point (cvo_evaluate_noalloc):
+// one copy of this array per device, held from the library's load until the
+// process ends.  Host code never uses the name itself (on the host it is
+// only a stand-in, not a device address): cvo_create looks up each device's
+// address once with hipGetSymbolAddress and every kernel gets that address.
+static __device__ __align__(256) unsigned char scratch[(size_t)CVO_NOALLOC_SCRATCH_MIB << 20];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_addr;  // device ordinal -> that device's copy of `scratch`
+
+// With `device` current: the device address of its copy of the array,
+// looked up on the first call for the device.
+hipError_t scratch_address(int device, void **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_addr.find(device);
+    if (it != g_scratch_addr.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[device] = ptr;
+    *out = ptr;
+    return hipSuccess;
+}
+}  // namespace
+
 // ------------------------------------------------------------------ handle
 struct cvo_context {
     int device = 0;
@@ -72,10 +104,23 @@ struct cvo_context {
     std::string graph_key;
     hipStream_t own_stream = nullptr;
 
+    // Allocation-free mode: buffers are carved from a fixed device array
+    // (base, cap) by a bump pointer that restarts with every call; a name
+    // asked for again within the call gets its earlier region back when it
+    // fits, as the arena below hands back the same buffer.
+    struct Fixed {
+        bool on = false;
+        char *base = nullptr;
+        size_t cap = 0, top = 0;
+        std::map<std::string, std::pair<size_t, size_t>> regions;  // name -> (offset, bytes)
+    } fixed;
+    std::string fixed_error;  // why the fixed scratch is unavailable, if it is
+
     void *get(const std::string &name, size_t bytes)
     {
-        Buf &b = bufs[name];
         if (bytes == 0) bytes = 16;
+        if (fixed.on) return get_fixed(name, bytes);
+        Buf &b = bufs[name];
         if (b.cap < bytes) {
             if (b.p) HIP_OK(hipFree(b.p));
             b.p = nullptr;
@@ -91,6 +136,22 @@ struct cvo_context {
             b.cap = cap;
         }
         return b.p;
+    }
+    void *get_fixed(const std::string &name, size_t bytes)
+    {
+        auto it = fixed.regions.find(name);
+        if (it != fixed.regions.end() && it->second.second >= bytes) return fixed.base + it->second.first;
+        const size_t need = (bytes + 255) & ~size_t(255);
+        if (need > fixed.cap - fixed.top)
+            throw CvoError(CVO_ERR_OUT_OF_MEMORY,
+                           "the allocation-free scratch (" + std::to_string(fixed.cap >> 20) +
+                               " MiB per device) is too small for this input: " + name + " needs " +
+                               std::to_string(need) + " bytes with " + std::to_string(fixed.cap - fixed.top) +
+                               " left");
+        const size_t off = fixed.top;
+        fixed.top += need;
+        fixed.regions[name] = {off, need};
+        return fixed.base + off;
     }
     template <class T> T *get_t(const std::string &name, size_t count)
     {
@@ -124,6 +185,12 @@ struct cvo_context {
     void upload(void *dst, const void *src, size_t bytes)
     {
         if (!bytes) return;
+        if (fixed.on) {
+            // no pinned staging: copy from the caller's memory and wait
+            HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream));
+            HIP_OK(hipStreamSynchronize(stream));
+            return;
+        }
         const size_t need = (bytes + 255) & ~size_t(255);
         if (ring_off && (ring_stream != stream || ring_off + need > ring_cap)) ring_drain();
         if (need > ring_cap) {
@@ -144,6 +211,11 @@ struct cvo_context {
     void download(void *dst, const void *src, size_t bytes)
     {
         if (!bytes) return;
+        if (fixed.on) {
+            HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, stream));
+            HIP_OK(hipStreamSynchronize(stream));
+            return;
+        }
         void *h = host(bytes);
         HIP_OK(hipMemcpyAsync(h, src, bytes, hipMemcpyDeviceToHost, stream));
         HIP_OK(hipStreamSynchronize(stream));
@@ -852,7 +924,9 @@ void build_views(cvo_context *ctx, Problem &p, const std::vector<CloudPtrs> &X, 
     for (size_t k = 0; k < ell.size(); ++k) rc[k] = p.kappa * ell[k];
     p.grid = build_grid(ctx, "fx", X, rc, p.lay, shape, &p.box_x);
     p.clus = build_clusters(ctx, "fz", Z, rc, p.lay, shape, &p.box_z);
-    p.plan = make_plan(ctx, "fp", p.clus, p.grid, p.d_state, 0, p.kappa, false);
+    // the fixed scratch of the allocation-free entry point is sized by the
+    // exact slot count (one host read) rather than its loose upper bound
+    p.plan = make_plan(ctx, "fp", p.clus, p.grid, p.d_state, 0, p.kappa, ctx->fixed.on);
     p.mom = moments(ctx, "fm", p.plan.nslots, p.lay.d4, false);
     p.nblk = reduce_blocks(p.clus.desc);
     p.partials = ctx->get_t<double>("partials", shape.size() * (size_t)p.nblk * kRedVals);
@@ -1162,6 +1236,17 @@ cvo_status cvo_create(cvo_handle *out, int device, void *stream)
         delete ctx;
         return CVO_ERR_DEVICE;
     }
+    // this device's copy of the allocation-free scratch; a failed lookup
+    // only disables cvo_evaluate_noalloc (it reports the error)
+    void *fixed = nullptr;
+    const hipError_t e = scratch_address(device, &fixed);
+    if (e == hipSuccess) {
+        ctx->fixed.base = static_cast<char *>(fixed);
+        ctx->fixed.cap = (size_t)CVO_NOALLOC_SCRATCH_MIB << 20;
+    } else {
+        ctx->fixed_error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        (void)hipGetLastError();
+    }
     *out = ctx;
     return CVO_OK;
 }
@@ -1216,6 +1301,45 @@ cvo_status cvo_evaluate(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z, co
 {
     return guarded(h, [&] {
         require(out != nullptr, "output is NULL");
+        PairState s;
+        evaluate_one(h, X, Z, spec, kp, T, &s);
+        out->F = s.F;
+        for (int k = 0; k < 6; ++k) out->grad[k] = s.grad[k];
+        out->curv = s.curv;
+        out->dF_dell = s.dF_dell;
+        out->r_max = s.r_max;
+        out->i_theta = s.i_theta;
+        out->n_pairs = (int64_t)s.n_pairs;
+    });
+}
+
+cvo_status cvo_evaluate_noalloc(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z, const cvo_feature_spec *spec,
+                                const cvo_kernel_params *kp, const double T[12], cvo_eval *out)
+{
+    return guarded(h, [&] {
+        require(out != nullptr, "output is NULL");
+        require(X != nullptr && Z != nullptr, "cloud is NULL");
+        require(X->n <= CVO_NOALLOC_MAX_POINTS && Z->n <= CVO_NOALLOC_MAX_POINTS,
+                "cvo_evaluate_noalloc takes at most " + std::to_string(CVO_NOALLOC_MAX_POINTS) +
+                    " points per cloud (got " + std::to_string(X->n) + " and " + std::to_string(Z->n) + ")");
+        if (!h->fixed.base) throw CvoError(CVO_ERR_DEVICE, "no allocation-free scratch: " + h->fixed_error);
+        // every buffer of this call comes from the fixed array; no events
+        struct Scope {
+            cvo_context *c;
+            bool prof;
+            explicit Scope(cvo_context *c_) : c(c_), prof(c_->profiling)
+            {
+                c->fixed.on = true;
+                c->fixed.top = 0;
+                c->fixed.regions.clear();
+                c->profiling = false;
+            }
+            ~Scope()
+            {
+                c->fixed.on = false;
+                c->profiling = prof;
+            }
+        } scope(h);
         PairState s;
         evaluate_one(h, X, Z, spec, kp, T, &s);
         out->F = s.F;
