@@ -82,6 +82,15 @@ typedef enum {
                                  moving cloud's points (rigid-body kinetic energy), direction G^-1 grad */
 #define CVO_METRIC_IDENTITY 1 /* plain coordinates: direction = grad */
 
+/* how the lengthscale moves during an ascent (cvo_align_params.ell_mode) */
+#define CVO_ELL_ANNEAL 0   /* Sec. IV: decay by `decay` whenever the indicator has stabilised */
+#define CVO_ELL_ADAPTIVE 1 /* Sec. VI (the lengthscale as an optimisation variable): every iteration
+                              sets ell to the maximiser of the lengthscale objective J of
+                              cvo_ell_objective at that iteration's (T, ell), clamped to
+                              [ell_min, ell_init] and to one factor `decay` of ell (down or up);
+                              converged when the step is below (eps_rot, eps_trans) and ell moved by
+                              at most ind_rel_tol * ell */
+
 /* trace record per iteration (cvo_align trace buffer, doubles) */
 #define CVO_TRACE_LEN 8 /* it, ell, F, |grad|, step tau, i_theta, |P|, curvature */
 
@@ -120,6 +129,8 @@ typedef struct {
     int64_t max_iter;    /* iteration cap, >= 1 */
     int32_t fixed_iters; /* nonzero: run exactly max_iter steps at ell_init, no annealing */
     int32_t metric;      /* CVO_METRIC_KINETIC (default) or CVO_METRIC_IDENTITY */
+    int32_t ell_mode;    /* CVO_ELL_ANNEAL (default) or CVO_ELL_ADAPTIVE */
+    int32_t reserved;    /* must be 0 */
 } cvo_align_params;
 
 typedef struct {
@@ -200,6 +211,20 @@ cvo_status cvo_gradient(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,
 cvo_status cvo_evaluate(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,
                         const cvo_feature_spec *spec, const cvo_kernel_params *kp,
                         const double T[12], cvo_eval *out);
+
+/* Lengthscale objective of the adaptive mode (Sec. VI, where the lengthscale
+ * becomes an optimisation variable; the paper gives no formula).  F of
+ * eq. (7) grows with ell, so ell is not chosen by F: it maximises the
+ * log-likelihood of the moved cloud under the kernel mixture centred on X,
+ *   J(T, ell) = sum_{j : W_j > 0} log W_j - 3 |Z+| log ell,
+ * W_j = sum_i w_ij over the pair set P frozen at (T, ell), Z+ the targets with
+ * W_j > 0.  For fixed per-target residuals r_j = sum_i w_ij s_ij / W_j its
+ * stationary point is ell_ml^2 = sum_{Z+} r_j / (3 |Z+|).
+ * out (host double[4]) = {J, dJ/dell (P frozen), ell_ml (0 if Z+ is empty),
+ * |Z+|}.  One pair pass; errors as cvo_inner_product. */
+cvo_status cvo_ell_objective(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,
+                             const cvo_feature_spec *spec, const cvo_kernel_params *kp,
+                             const double T[12], double out[4]);
 
 /* Allocation-free form of cvo_evaluate, for callers that cannot allocate
  * device memory (code that must not call hipMalloc/hipFree, e.g. inside a

@@ -26,11 +26,12 @@ CVO_OK, CVO_ERR_INVALID_ARGUMENT, CVO_ERR_OUT_OF_MEMORY, CVO_ERR_DEVICE, CVO_ERR
 CVO_SE, CVO_LIN = 0, 1
 CVO_CONVERGED, CVO_MAX_ITER, CVO_NO_OVERLAP, CVO_STATIONARY = 1, 2, 3, 4
 CVO_METRIC_KINETIC, CVO_METRIC_IDENTITY = 0, 1
+CVO_ELL_ANNEAL, CVO_ELL_ADAPTIVE = 0, 1
 CVO_TRACE_LEN = 8
 MAX_BLOCKS = 8
 
 EXPORTS = ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_last_error", "cvo_inner_product",
-           "cvo_gradient", "cvo_evaluate", "cvo_evaluate_noalloc", "cvo_metric", "cvo_cosine", "cvo_align", "cvo_align_replay",
+           "cvo_gradient", "cvo_evaluate", "cvo_evaluate_noalloc", "cvo_ell_objective", "cvo_metric", "cvo_cosine", "cvo_align", "cvo_align_replay",
            "cvo_inner_product_backward",
            "cvo_align_batched", "cvo_odometry", "cvo_select_points", "cvo_get_tuning", "cvo_set_tuning", "cvo_autotune",
            "cvo_set_profiling", "cvo_get_timing")
@@ -60,7 +61,8 @@ class cvo_align_params(C.Structure):
     _fields_ = [("ell_init", C.c_double), ("ell_min", C.c_double), ("decay", C.c_double),
                 ("ind_rel_tol", C.c_double), ("eps_rot", C.c_double), ("eps_trans", C.c_double),
                 ("step_lambda", C.c_double), ("sigma", C.c_double), ("kappa", C.c_double),
-                ("max_iter", C.c_int64), ("fixed_iters", C.c_int32), ("metric", C.c_int32)]
+                ("max_iter", C.c_int64), ("fixed_iters", C.c_int32), ("metric", C.c_int32),
+                ("ell_mode", C.c_int32), ("reserved", C.c_int32)]
 
 
 class cvo_align_report(C.Structure):
@@ -114,6 +116,7 @@ def load_library(path: str = LIB_PATH):
     lib.cvo_gradient.argtypes = common + [P(C.c_double), C.c_void_p, P(C.c_int64)]
     lib.cvo_evaluate.argtypes = common + [P(cvo_eval)]
     lib.cvo_evaluate_noalloc.argtypes = common + [P(cvo_eval)]
+    lib.cvo_ell_objective.argtypes = common + [C.c_void_p]
     lib.cvo_metric.argtypes = common + [P(C.c_double)]
     lib.cvo_cosine.argtypes = common + [P(C.c_double), C.c_void_p]
     lib.cvo_align.argtypes = [H, P(cvo_cloud), P(cvo_cloud), P(cvo_feature_spec), P(cvo_align_params),
@@ -314,7 +317,7 @@ def cvo_metric(X, Z, T, ell, U=None, V=None, spec=None, sigma=1.0, kappa=3.0):
 
 DEFAULT_ALIGN = dict(ell_init=0.1, ell_min=0.1, decay=0.98, ind_rel_tol=1e-3, eps_rot=1e-6, eps_trans=1e-6,
                      step_lambda=1.0, sigma=1.0, kappa=3.0, max_iter=4000, fixed_iters=False,
-                     metric=CVO_METRIC_KINETIC)
+                     metric=CVO_METRIC_KINETIC, ell_mode=CVO_ELL_ANNEAL)
 
 
 def _align_params(params):
@@ -322,7 +325,7 @@ def _align_params(params):
     p.update(params or {})
     return cvo_align_params(p["ell_init"], p["ell_min"], p["decay"], p["ind_rel_tol"], p["eps_rot"],
                             p["eps_trans"], p["step_lambda"], p["sigma"], p["kappa"], int(p["max_iter"]),
-                            int(bool(p["fixed_iters"])), int(p["metric"])), p
+                            int(bool(p["fixed_iters"])), int(p["metric"]), int(p["ell_mode"]), 0), p
 
 
 def _report(r):
@@ -488,6 +491,21 @@ def cvo_inner_product_backward(X, Z, T, ell, gF=1.0, U=None, V=None, spec=None, 
         ptr(dU), ptr(dV), C.byref(dl) if "ell" in need else None), h)
     del keep
     return {"dX": dX, "dZ": dZ, "dU": dU, "dV": dV, "dell": dl.value if "ell" in need else None}
+
+
+def cvo_ell_objective(X, Z, T, ell, U=None, V=None, spec=None, sigma=1.0, kappa=3.0):
+    """Lengthscale objective of the adaptive mode: J = sum_{W_j > 0} log W_j -
+    3 |Z+| log ell on the pair set frozen at (T, ell), dJ/dell, its maximiser
+    ell_ml and |Z+| (cvo_ell_objective)."""
+    h = handle()
+    cx, cz, keep, sp = _prep(X, Z, U, V, spec)
+    kp = cvo_kernel_params(ell, sigma, kappa)
+    Tp = _pose(T)
+    out = np.zeros(4)
+    _check(load_library().cvo_ell_objective(h, C.byref(cx), C.byref(cz), C.byref(sp), C.byref(kp),
+                                            Tp.ctypes.data, out.ctypes.data), h)
+    del keep
+    return {"J": out[0], "dJ_dell": out[1], "ell_ml": out[2], "n_plus": int(out[3])}
 
 
 def cvo_evaluate_noalloc(X, Z, T, ell, U=None, V=None, spec=None, sigma=1.0, kappa=3.0):

@@ -911,6 +911,7 @@ struct Problem {
     int nblk = 1;
     double kappa = 3.0;
     float sig2 = 1.f;
+    int ellobj = 0;         // reduce the lengthscale objective's sums too
     BoxCache box_x, box_z;  // bounding boxes from the first view build
 };
 
@@ -965,6 +966,7 @@ void iteration_args(const Problem &p, int mode, double *trace, long long trace_r
     r.trace_rows = trace_rows;
     r.nblk = p.nblk;
     r.mode = mode;
+    r.ellobj = p.ellobj;
 }
 
 void enqueue_iteration(cvo_context *ctx, Problem &p, int mode, double *trace, long long trace_rows, bool timed)
@@ -1022,6 +1024,8 @@ AlignConst const_for(const cvo_align_params *ap, long long N, long long M)
         a.max_iter = ap->max_iter;
         a.fixed_iters = ap->fixed_iters;
         a.metric = ap->metric;
+        a.ell_mode = ap->ell_mode;
+        a.ell_init = ap->ell_init;
         a.kappa = ap->kappa;
     } else {
         a.max_iter = 1;
@@ -1049,11 +1053,13 @@ void check_align_params(const cvo_align_params *ap)
     require(!std::isnan(ap->kappa) && ap->kappa > 0.0, "kappa must be > 0");
     require(ap->max_iter >= 1, "max_iter must be >= 1");
     require(ap->metric == CVO_METRIC_KINETIC || ap->metric == CVO_METRIC_IDENTITY, "unknown metric");
+    require(ap->ell_mode == CVO_ELL_ANNEAL || ap->ell_mode == CVO_ELL_ADAPTIVE, "unknown ell_mode");
+    require(ap->reserved == 0, "reserved must be 0");
 }
 
 // single forward evaluation
 void evaluate_one(cvo_context *ctx, const cvo_cloud *X, const cvo_cloud *Z, const cvo_feature_spec *spec,
-                  const cvo_kernel_params *kp, const double *T, PairState *out)
+                  const cvo_kernel_params *kp, const double *T, PairState *out, bool ellobj = false)
 {
     check_spec(spec);
     const int D = spec_dim(spec);
@@ -1070,6 +1076,7 @@ void evaluate_one(cvo_context *ctx, const cvo_cloud *X, const cvo_cloud *Z, cons
     p.kappa = kp->kappa;
     p.lay = make_layout(spec, kp->sigma);
     p.sig2 = p.lay.sig2;
+    p.ellobj = ellobj ? 1 : 0;
     AlignConst ac = const_for(nullptr, X->n, Z->n);
     setup_problem(ctx, p, {to_ptrs(X)}, {to_ptrs(Z)}, {s0}, {ac});
     enqueue_iteration(ctx, p, 0, nullptr, 0, ctx->profiling);
@@ -1117,6 +1124,8 @@ void align_many(cvo_context *ctx, const std::vector<CloudPtrs> &X, const std::ve
     p.sig2 = p.lay.sig2;
     const bool cut = std::isfinite(p.kappa);
     const bool adapt = cut && ctx->tuning.adaptive;
+    for (int b = 0; b < B; ++b)
+        if (prm[b].ell_mode == CVO_ELL_ADAPTIVE && !prm[b].fixed_iters && !d_sched) p.ellobj = 1;
     std::vector<PairState> st(B);
     std::vector<AlignConst> ac(B);
     long long trace_rows = 0;
@@ -1310,6 +1319,21 @@ cvo_status cvo_evaluate(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z, co
         out->r_max = s.r_max;
         out->i_theta = s.i_theta;
         out->n_pairs = (int64_t)s.n_pairs;
+    });
+}
+
+cvo_status cvo_ell_objective(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z, const cvo_feature_spec *spec,
+                             const cvo_kernel_params *kp, const double T[12], double out[4])
+{
+    return guarded(h, [&] {
+        require(out != nullptr, "output is NULL");
+        PairState s;
+        evaluate_one(h, X, Z, spec, kp, T, &s, true);
+        const bool empty = X->n == 0 || Z->n == 0;
+        out[0] = empty ? 0.0 : s.J;
+        out[1] = empty ? 0.0 : s.dJ_dell;
+        out[2] = empty ? 0.0 : s.ell_ml;
+        out[3] = empty ? 0.0 : s.zplus;
     });
 }
 

@@ -29,7 +29,7 @@ constexpr int kQueueCap = 80;    // LDS candidate queue per wave
 constexpr int kQueueFlush = 16;  // process the queue once it holds this many (cap >= flush + 64)
 constexpr int kTraceLen = 8;
 constexpr int kRadixTile = 1024;  // keys per workgroup and pass of the radix sort
-constexpr int kRedVals = 40;     // values reduced per pair by the reduction kernel
+constexpr int kRedVals = 48;     // values reduced per pair by the reduction kernel
 constexpr int kRedThreads = 256;
 
 enum Status { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAX_ITER = 2, ST_NO_OVERLAP = 3, ST_STATIONARY = 4 };
@@ -45,6 +45,9 @@ struct alignas(16) PairState {
     double n_pairs;      // |P| of the last evaluation (exact integer in a double)
     double total_pairs;  // sum of |P| over the registration
     double rc_build;     // cutoff radius the current views were built for
+    // lengthscale objective at the last evaluation (when it was asked for):
+    // J = sum_{W_j > 0} log W_j - 3 |Z+| log ell, dJ/dell, its maximiser, |Z+|
+    double J, dJ_dell, ell_ml, zplus;
     long long it;        // steps taken
     int status;          // Status
     int done;            // nonzero: later launches skip this pair
@@ -69,6 +72,8 @@ struct alignas(16) AlignConst {
     long long max_iter;
     int fixed_iters;
     int metric;          // 0: kinetic-energy metric of the moving cloud, 1: identity
+    int ell_mode;        // 0: annealing (Sec. IV), 1: adaptive (maximiser of the lengthscale objective)
+    double ell_init;     // adaptive mode: upper clamp of ell
     int adaptive;        // nonzero: also pause when the density class drops below cls_built
     double cls_t[3];     // pairs per query where density classes 3, 2 and 1 begin
     const double *ell_sched;  // replay: lengthscale of every iteration (device; null: annealing)

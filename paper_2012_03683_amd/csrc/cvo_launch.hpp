@@ -75,6 +75,7 @@ struct ReduceArgs {
     long long trace_rows;
     int nblk;
     int mode;                  // 0: evaluate only, 1: evaluate and take an ascent step
+    int ellobj;                // nonzero: also reduce the lengthscale objective's sums
 };
 void launch_reduce(const ReduceArgs &a, int B, hipStream_t s);
 

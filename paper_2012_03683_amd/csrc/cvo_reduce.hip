@@ -13,7 +13,10 @@
 //              H_ww = -Z A Z + (D z'^T + z' D^T)/(2 ell^2) - (D.z') I/ell^2
 //              H_wv =  Z A - [D]_x /(2 ell^2),   H_vv = A
 //   tr S / ell^3 = dF/dell (cutoff held fixed), |P| = sum n_j,
-//   r_max = max_j |z'_j|.
+//   r_max = max_j |z'_j|,
+// and, for the adaptive lengthscale (Sec. VI), over the targets with W_j > 0:
+//   sum log W_j, sum r_j with r_j = tr S_j / W_j (the target's weighted mean
+//   squared residual), and their number |Z+|.
 // The curvature along a direction d is d^T H d.  Each block reduces a fixed
 // slice of the queries in a fixed tree order; a second launch, one workgroup
 // per pair, combines the block partials in a fixed order and, in step mode,
@@ -22,10 +25,11 @@
 
 namespace cvo {
 
-// accumulator slots
+// accumulator slots (R_LOGW .. R_ZP: the lengthscale objective's sums over
+// the targets with W_j > 0, reduced only when asked for; 43 .. 47 unused)
 enum {
     R_F = 0, R_OM = 1, R_V = 4, R_HWW = 7, R_HWV = 13, R_HVV = 22, R_TRS = 28, R_N = 29, R_RMAX = 30,
-    R_ZS = 31, R_ZZ = 34, R_END = 40
+    R_ZS = 31, R_ZZ = 34, R_LOGW = 40, R_RSUM = 41, R_ZP = 42, R_END = 48
 };
 
 // Solve G d = g for a symmetric positive definite 6x6 G by Cholesky
@@ -175,6 +179,14 @@ __device__ __forceinline__ void finalize_local(PairState &st, const AlignConst &
     st.r_max = tot[R_RMAX];
     st.dF_dell = tot[R_TRS] / (ell * ell * ell);
     st.n_pairs = np;
+    {
+        // lengthscale objective J = sum log W_j - 3 |Z+| log ell (zero unless reduced)
+        const double mp = tot[R_ZP];
+        st.J = tot[R_LOGW] - 3.0 * mp * log(ell);
+        st.dJ_dell = tot[R_RSUM] / (ell * ell * ell) - 3.0 * mp / ell;
+        st.ell_ml = mp > 0.0 ? sqrt(tot[R_RSUM] / (3.0 * mp)) : 0.0;
+        st.zplus = mp;
+    }
 #pragma unroll
     for (int k = 0; k < 6; ++k) st.grad[k] = g[k];
     const double gn2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2] + g[3] * g[3] + g[4] * g[4] + g[5] * g[5];
@@ -248,6 +260,23 @@ __device__ __forceinline__ void finalize_local(PairState &st, const AlignConst &
             return;
         }
         st.ell = ac.ell_sched[it + 1];
+    } else if (ac.ell_mode == 1 && !ac.fixed_iters) {
+        // adaptive lengthscale: the objective's maximiser at this iteration's
+        // (T, ell), clamped to [ell_min, ell_init] and to one factor `decay`
+        double next = ell;
+        if (st.ell_ml > 0.0) {
+            double lo = ac.decay * ell, hi = ell / ac.decay;
+            if (lo < ac.ell_min) lo = ac.ell_min;
+            if (hi > ac.ell_init) hi = ac.ell_init;
+            next = st.ell_ml < lo ? lo : (st.ell_ml > hi ? hi : st.ell_ml);
+        }
+        const bool still = fabs(next - ell) <= ac.ind_rel_tol * ell;
+        st.ell = next;
+        if (still && tau * nw < ac.eps_rot && tau * nv < ac.eps_trans) {
+            st.status = ST_CONVERGED;
+            st.done = 1;
+            return;
+        }
     } else if (!ac.fixed_iters) {
         const double ip = st.i_prev;
         if (isfinite(ip) && fabs(ind - ip) <= ac.ind_rel_tol * fabs(ind) && ell > ac.ell_min) {
@@ -273,6 +302,10 @@ __device__ __forceinline__ void finalize_local(PairState &st, const AlignConst &
     // alone, so where views change does not depend on how many iterations
     // are enqueued between host checks.
     if (isfinite(ac.kappa) && ac.kappa * st.ell < ac.rebuild_ratio * st.rc_build) st.pause = 1;
+    // (an adaptive lengthscale may also grow: rebuild once the cutoff has
+    // grown by the same ratio)
+    if (isfinite(ac.kappa) && ac.rebuild_ratio < 1.0 && ac.kappa * st.ell * ac.rebuild_ratio > st.rc_build)
+        st.pause = 1;
     if (ac.adaptive && st.cls_built >= 0 && density_class(np * ac.inv_m, ac.cls_t) < st.cls_built) st.pause = 1;
 }
 
@@ -285,7 +318,7 @@ __device__ void finalize_pair(PairState *st_g, const AlignConst *ac_g, const dou
     *st_g = st;
 }
 
-static_assert(kRedThreads == 256 && R_END == 40 && R_END <= kRedVals, "reduction layout");
+static_assert(kRedThreads == 256 && R_END == 48 && R_END <= kRedVals, "reduction layout");
 
 __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
 {
@@ -371,8 +404,14 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
         acc[R_OM + 2] += z[0] * Dt[1] - z[1] * Dt[0];
 #pragma unroll
         for (int k = 0; k < 3; ++k) acc[R_V + k] += Dt[k];
-        acc[R_TRS] += S6[0] + S6[3] + S6[5];
+        const double trs = S6[0] + S6[3] + S6[5];
+        acc[R_TRS] += trs;
         acc[R_N] += (double)nj;
+        if (a.ellobj && Wt > 0.0) {
+            acc[R_LOGW] += log(Wt);
+            acc[R_RSUM] += trs / Wt;
+            acc[R_ZP] += 1.0;
+        }
         // A = S/ell^4 - W I/ell^2
         const double A[3][3] = {{S6[0] * il4 - Wt * il2, S6[1] * il4, S6[2] * il4},
                                 {S6[1] * il4, S6[3] * il4 - Wt * il2, S6[4] * il4},
@@ -401,11 +440,11 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
             for (int k = 0; k < 3; ++k) acc[R_HWV + 3 * r + k] += ZA[r][k] - 0.5 * Dx[r][k] * il2;
     }
 
-    // block reduction, 20 values at a time through LDS: every thread stores
-    // its 20 values; thread (value kv = t / 8, stripe s = t % 8), t < 160,
+    // block reduction, 24 values at a time through LDS: every thread stores
+    // its 24 values; thread (value kv = t / 8, stripe s = t % 8), t < 192,
     // adds the entries s, s + 8, ... of its value, and an 8-lane shuffle tree
     // finishes.  Fixed order throughout.
-    constexpr int kChunk = 20, kStripes = 8;
+    constexpr int kChunk = 24, kStripes = 8;
     __shared__ double red[kChunk][kRedThreads];
     const int tid = threadIdx.x;
     double *part = a.partials + ((long long)b * a.nblk + blockIdx.x) * kRedVals;

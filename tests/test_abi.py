@@ -47,7 +47,7 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(cvo.cvo_cloud) == 24
     assert ctypes.sizeof(cvo.cvo_feature_spec) == 4 + 32 + 32 + 4 + 64 + 64
     assert ctypes.sizeof(cvo.cvo_kernel_params) == 24
-    assert ctypes.sizeof(cvo.cvo_align_params) == 9 * 8 + 8 + 8
+    assert ctypes.sizeof(cvo.cvo_align_params) == 9 * 8 + 8 + 16
     assert ctypes.sizeof(cvo.cvo_align_report) == 56
     assert ctypes.sizeof(cvo.cvo_eval) == 8 * 12
     assert ctypes.sizeof(cvo.cvo_tuning) == 48
