@@ -1,0 +1,106 @@
+"""Full-size registrations against the oracle's converged runs (Problem 1,
+eq. (1), with the annealing of Sec. IV).
+
+The oracle's runs of the stereo-outdoor pair (30k + 30k, 5 SE + 19 LIN,
+ell 0.95 -> 0.1) and the RGB-D-indoor pair (40k + 40k, 5 SE, 0.1 -> 0.05) are
+stored in golden/full_size_registrations.json by golden/make_full_size.py
+(it calls only the input generators and the oracle).  The test regenerates
+the inputs, checks they hash to what the oracle was run on, then
+  * registers them with cvo_align: same status and final lengthscale, and the
+    converged pose within 1e-4 rad / 1e-4 m of the oracle's;
+  * replays the oracle's lengthscale sequence with cvo_align_replay: every
+    iterate's F within 1e-5 (all weights are positive, so |F| is the
+    absolute sum), |P| exact at the first iterate (same pose) and within 1e-5
+    at later ones (their poses differ by rounding, so pairs lying within
+    ~1e-8 m of the cutoff sphere can flip), and the final pose within
+    1e-4 rad / 1e-4 m."""
+import importlib.util
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2012_03683_amd import synth
+
+from gpu_util import pose_error, to_dev
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden", "full_size_registrations.json")
+
+
+def _golden_module():
+    spec = importlib.util.spec_from_file_location("make_full_size", os.path.join(HERE, "golden", "make_full_size.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+@pytest.fixture(scope="module")
+def cvo():
+    import paper_2012_03683_amd as m
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU in this environment")
+    m.load_library()
+    return m
+
+
+@pytest.fixture(scope="module")
+def golden():
+    with open(GOLDEN) as fh:
+        return json.load(fh)
+
+
+def _pair(which, golden):
+    mod = _golden_module()
+    p = mod.WORKLOADS[which][1]()
+    g = golden[which]
+    assert mod.input_hash(p) == g["input_sha256"], "regenerated inputs differ from the oracle's"
+    return p, g
+
+
+@pytest.mark.parametrize("which", ["stereo", "rgbd"])
+def test_full_size_converged_pose_matches_oracle(cvo, golden, which):
+    p, g = _pair(which, golden)
+    X, Z, U, V = to_dev(p, torch)
+    print(f"{which}: cvo_align at full size", flush=True)
+    T, rep, tr = cvo.cvo_align(X, Z, U, V, p.spec, g["params"], trace=True)
+    To = np.array(g["T"])
+    ang, dt = pose_error(T, To)
+    print(which, "gpu", rep, "oracle", g["report"], "pose deviation", ang, dt, flush=True)
+    assert rep["status"] == g["report"]["status"]
+    assert rep["final_ell"] == g["report"]["final_ell"]
+    assert ang < 1e-4 and dt < 1e-4
+    # the lengthscale sequence is the oracle's wherever the annealing
+    # decisions agree (they can flip only at the stabilisation threshold)
+    n = min(len(tr), len(g["trace"]["ell"]))
+    same = tr[:n, 1] == np.array(g["trace"]["ell"][:n])
+    agree = n if same.all() else int(np.argmin(same))
+    print(which, "iterations", len(tr), len(g["trace"]["ell"]), "schedules agree through", agree, flush=True)
+
+
+@pytest.mark.parametrize("which", ["stereo", "rgbd"])
+def test_full_size_replay_iterate_by_iterate(cvo, golden, which):
+    p, g = _pair(which, golden)
+    X, Z, U, V = to_dev(p, torch)
+    sched = np.array(g["trace"]["ell"])
+    print(f"{which}: replay of the oracle's {len(sched)} lengthscales", flush=True)
+    T, rep, tr = cvo.cvo_align_replay(X, Z, U, V, p.spec, sched, g["params"], trace=True)
+    assert rep["iterations"] == len(sched) and rep["status"] == cvo.CVO_MAX_ITER
+    np.testing.assert_array_equal(tr[:, 1], sched)
+    np.testing.assert_allclose(tr[:, 2], g["trace"]["F"], rtol=1e-5)
+    npairs = np.array(g["trace"]["n_pairs"])
+    # the first iterate is at the same pose on both sides: |P| exact.  Later
+    # poses differ by rounding (~1e-8 m); with millions of pairs per
+    # iterate, a few lie that close to the cutoff sphere and can flip.
+    assert tr[0, 6] == npairs[0]
+    differ = np.flatnonzero(tr[:, 6] != npairs)
+    print(which, "iterations with a different |P|:", differ.size, "largest difference",
+          int(np.max(np.abs(tr[:, 6] - npairs))), flush=True)
+    np.testing.assert_allclose(tr[:, 6], npairs, rtol=1e-5)
+    ang, dt = pose_error(T, np.array(g["T"]))
+    print(which, "replay final pose deviation", ang, dt, flush=True)
+    assert ang < 1e-4 and dt < 1e-4
