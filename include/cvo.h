@@ -172,12 +172,19 @@ typedef struct {
 } cvo_tuning;
 
 /* Per-handle timing of the dominant kernel, measured with HIP events on the
- * handle's stream while profiling is enabled (cvo_set_profiling). */
+ * handle's stream while profiling is enabled (cvo_set_profiling), and counts
+ * of launches, graphs, view builds and host waits (always kept; every
+ * cvo_set_profiling call resets them). */
 typedef struct {
     int64_t pair_launches;     /* pair-pass launches timed */
     double pair_ms;            /* summed event time of those launches */
     int64_t pair_count;        /* summed |P| of the timed launches (when known) */
-    int64_t evaluations;       /* pair-pass evaluations, timed or not */
+    int64_t evaluations;       /* pair-pass launches enqueued, timed or not (a graph replay counts
+                                  each pair pass it holds) */
+    int64_t graph_launches;    /* captured iteration graphs replayed */
+    int64_t graph_captures;    /* iteration graphs captured and instantiated */
+    int64_t view_builds;       /* builds of the grid and cluster views and the work plan */
+    int64_t host_waits;        /* waits of the host for the handle's stream */
 } cvo_timing;
 
 /* Create a handle on `device` (HIP ordinal) that enqueues on `stream`
@@ -373,7 +380,7 @@ cvo_status cvo_autotune(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,
                         const double T[12], cvo_tuning *chosen);
 
 /* Enable (nonzero) or disable HIP-event timing of every pair-pass launch;
- * enabling resets the counters. */
+ * either call resets the timing and the counters. */
 cvo_status cvo_set_profiling(cvo_handle h, int32_t enable);
 cvo_status cvo_get_timing(cvo_handle h, cvo_timing *out);
 

@@ -89,7 +89,8 @@ class cvo_camera(C.Structure):
 
 class cvo_timing(C.Structure):
     _fields_ = [("pair_launches", C.c_int64), ("pair_ms", C.c_double), ("pair_count", C.c_int64),
-                ("evaluations", C.c_int64)]
+                ("evaluations", C.c_int64), ("graph_launches", C.c_int64), ("graph_captures", C.c_int64),
+                ("view_builds", C.c_int64), ("host_waits", C.c_int64)]
 
 
 _lib = None
@@ -550,8 +551,7 @@ def cvo_get_timing():
     h = handle()
     t = cvo_timing()
     _check(load_library().cvo_get_timing(h, C.byref(t)), h)
-    return {"pair_launches": int(t.pair_launches), "pair_ms": t.pair_ms, "pair_count": int(t.pair_count),
-            "evaluations": int(t.evaluations)}
+    return {k: (getattr(t, k) if k == "pair_ms" else int(getattr(t, k))) for k, _ in cvo_timing._fields_}
 
 
 # ---------------------------------------------------------------- autograd

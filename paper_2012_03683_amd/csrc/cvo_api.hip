@@ -94,7 +94,7 @@ struct cvo_context {
     size_t pinned_cap = 0;
     cvo_tuning tuning{16, 1.0, 0.5, 0.6, 16, 512, 1};
     bool profiling = false;
-    cvo_timing timing{0, 0.0, 0, 0};
+    cvo_timing timing{0, 0.0, 0, 0, 0, 0, 0, 0};
     std::vector<hipEvent_t> ev_free;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
     std::map<std::string, cvo_tuning> tune_cache;
@@ -178,6 +178,7 @@ struct cvo_context {
     void ring_drain()
     {
         if (ring_off) {
+            timing.host_waits += 1;
             HIP_OK(hipStreamSynchronize(ring_stream));
             ring_off = 0;
         }
@@ -211,6 +212,7 @@ struct cvo_context {
     void download(void *dst, const void *src, size_t bytes)
     {
         if (!bytes) return;
+        timing.host_waits += 1;
         if (fixed.on) {
             HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, stream));
             HIP_OK(hipStreamSynchronize(stream));
@@ -921,6 +923,7 @@ void build_views(cvo_context *ctx, Problem &p, const std::vector<CloudPtrs> &X, 
                  const std::vector<double> &ell, const std::vector<ViewShape> &shape)
 {
     p.shape = shape;
+    ctx->timing.view_builds += 1;
     std::vector<double> rc(ell.size());
     for (size_t k = 0; k < ell.size(); ++k) rc[k] = p.kappa * ell[k];
     p.grid = build_grid(ctx, "fx", X, rc, p.lay, shape, &p.box_x);
@@ -1177,8 +1180,12 @@ void align_many(cvo_context *ctx, const std::vector<CloudPtrs> &X, const std::ve
                 HIP_OK(hipGraphInstantiate(&ctx->graph, g, nullptr, nullptr, 0));
                 HIP_OK(hipGraphDestroy(g));
                 ctx->graph_key = key;
+                ctx->timing.graph_captures += 1;
+                ctx->timing.evaluations -= U;  // counted per replay below, not at capture
             }
             HIP_OK(hipGraphLaunch(ctx->graph, ctx->stream));
+            ctx->timing.graph_launches += 1;
+            ctx->timing.evaluations += U;
         } else {
             for (int u = 0; u < U; ++u) enqueue_iteration(ctx, p, 1, d_trace, trace_rows, ctx->profiling);
         }
@@ -1726,7 +1733,7 @@ cvo_status cvo_set_profiling(cvo_handle h, int32_t enable)
 {
     if (!h) return CVO_ERR_INVALID_ARGUMENT;
     h->profiling = enable != 0;
-    if (h->profiling) h->timing = cvo_timing{0, 0.0, 0, 0};
+    h->timing = cvo_timing{0, 0.0, 0, 0, 0, 0, 0, 0};
     return CVO_OK;
 }
 
