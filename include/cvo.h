@@ -40,7 +40,8 @@
  *   - A handle is not thread safe: one call at a time per handle.
  *
  * Errors: every call returns a cvo_status; on failure cvo_last_error()
- * gives a message.  N = 0 or M = 0 is not an error (F = 0, gradient 0,
+ * gives a message.  A pose must be rigid: max |R^T R - I| <= 1e-9 and
+ * det R > 0, with finite entries (else CVO_ERR_INVALID_ARGUMENT).  N = 0 or M = 0 is not an error (F = 0, gradient 0,
  * |P| = 0; cvo_align reports CVO_NO_OVERLAP and returns T_init).
  * Non-convergence is a report status, never an error code.
  */
@@ -154,6 +155,14 @@ typedef struct {
     int64_t n_pairs; /* |P| */
 } cvo_eval;
 
+/* Query clusters (cvo_tuning.cluster_rule): OCTREE takes the largest aligned
+ * Morton (octree) block with at most cluster_max points and an edge within
+ * cluster_factor * r_c; CHUNKS cuts the Morton-ordered points into runs of
+ * cluster_max and halves a run until its bounding box edge is within
+ * cluster_factor * r_c (parts of cluster_max / 2^k points). */
+#define CVO_CLUSTER_OCTREE 0
+#define CVO_CLUSTER_CHUNKS 1
+
 /* Tuning knobs (picked by cvo_autotune or set by hand). */
 typedef struct {
     int32_t cluster_max;   /* max query points per cluster: 8, 16, 32 or 64 */
@@ -162,13 +171,14 @@ typedef struct {
     double rebuild_ratio;  /* rebuild grids when cutoff < rebuild_ratio * cutoff at build, in (0, 1] */
     int32_t unroll;        /* iterations enqueued per host check / per captured graph, 1..64 */
     int32_t piece_work;    /* query x candidate products per unit of pair-pass work, 256..2^24 */
-    int32_t adaptive;      /* 0 or 1.  1: a registration re-chooses cluster_max, cell_factor and
-                            * cluster_factor at every view build from the in-cutoff pairs per query point
-                            * of its latest iteration.  Padded feature rows of more than 8 floats:
-                            * >= 2000: 64, 0.5, 0.5; >= 500: 32, 0.5, 0.5; >= 200: 32, 1.0, 1.5;
-                            * fewer: 16, 1.0, 1.0.  Rows of at most 8 floats: >= 500: 64, 0.5, 0.5;
-                            * >= 100: 32, 1.0, 1.5; fewer: 16, 1.0, 1.5.  Not yet measured: the three
-                            * fields above.  One-shot calls always use the fields above. */
+    int32_t cluster_rule;  /* how query clusters are formed: CVO_CLUSTER_OCTREE or CVO_CLUSTER_CHUNKS */
+    int32_t adaptive;      /* 0 or 1.  1: a registration re-chooses cluster_max, cell_factor,
+                            * cluster_factor and cluster_rule at every view build from the in-cutoff
+                            * pairs per query point of its latest iteration (chunk clusters throughout).
+                            * Padded feature rows of more than 8 floats: >= 500: 32, 0.5, 0.5;
+                            * >= 200: 16, 0.5, 1.0; fewer: 16, 1.0, 1.0.  Rows of at most 8 floats:
+                            * >= 100: 32, 0.5, 1.0; fewer: 16, 1.0, 1.5.  Not yet measured: the fields
+                            * above.  One-shot calls always use the fields above. */
 } cvo_tuning;
 
 /* Per-handle timing of the dominant kernel, measured with HIP events on the
@@ -185,6 +195,7 @@ typedef struct {
     int64_t graph_captures;    /* iteration graphs captured and instantiated */
     int64_t view_builds;       /* builds of the grid and cluster views and the work plan */
     int64_t host_waits;        /* waits of the host for the handle's stream */
+    int64_t tuned_view_shapes; /* view shapes a registration took from the autotuned class table */
 } cvo_timing;
 
 /* Create a handle on `device` (HIP ordinal) that enqueues on `stream`
@@ -371,13 +382,34 @@ cvo_status cvo_select_points(cvo_handle h, const uint8_t *gray, const float *dep
 cvo_status cvo_get_tuning(cvo_handle h, cvo_tuning *out);
 cvo_status cvo_set_tuning(cvo_handle h, const cvo_tuning *in);
 
-/* Time a pair pass of (X, Z, spec, kp, T) under each candidate tuning in a
- * built-in search space and keep the fastest; the choice is cached in the
- * handle per (point-count, feature-layout, lengthscale band) class.  If
- * chosen is non-NULL it receives the winner. */
+/* Project-written autotuner of the bin (grid cell) and tile (query cluster)
+ * sizes.  Times the pair pass of (X, Z, spec, kp, T) under each view shape of
+ * a search space -- cluster rule (octree, chunks) x points per cluster (16,
+ * 32, 64) x cell edge (0.5, 1.0 r_c) x cluster edge cap (0.5, 1.0, 1.5 r_c),
+ * median of 3 timed launches after one untimed -- and keeps the fastest:
+ *   - as the handle's one-shot shape (cluster_max, cell_factor,
+ *     cluster_factor, cluster_rule; the other tuning fields are unchanged),
+ *     cached per (point-count, feature-dimension, lengthscale band) class;
+ *   - as the shape of this evaluation's density class (its in-cutoff pairs
+ *     per query point, and whether feature rows fit in 8 floats), which
+ *     adaptive registrations -- plain and batched -- then use at every view
+ *     build of that class instead of the built-in table.
+ * If chosen is non-NULL it receives the resulting tuning.  Both clouds must
+ * be non-empty (CVO_ERR_INVALID_ARGUMENT). */
 cvo_status cvo_autotune(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z,
                         const cvo_feature_spec *spec, const cvo_kernel_params *kp,
                         const double T[12], cvo_tuning *chosen);
+
+/* Persist the autotuner's choices (the density-class table and the one-shot
+ * cache) to a text file, and merge such a file into a handle, so tuning
+ * survives cvo_destroy and carries over to later processes.  Load rejects a
+ * file that is not a tuning file or holds a shape outside the allowed ranges
+ * (CVO_ERR_INVALID_ARGUMENT, nothing merged). */
+cvo_status cvo_save_tuning(cvo_handle h, const char *path);
+cvo_status cvo_load_tuning(cvo_handle h, const char *path);
+/* Forget the autotuner's class table and one-shot cache (registrations fall
+ * back to the built-in table; the tuning fields are unchanged). */
+cvo_status cvo_clear_tuning(cvo_handle h);
 
 /* Enable (nonzero) or disable HIP-event timing of every pair-pass launch;
  * either call resets the timing and the counters. */

@@ -27,6 +27,7 @@ CVO_SE, CVO_LIN = 0, 1
 CVO_CONVERGED, CVO_MAX_ITER, CVO_NO_OVERLAP, CVO_STATIONARY = 1, 2, 3, 4
 CVO_METRIC_KINETIC, CVO_METRIC_IDENTITY = 0, 1
 CVO_ELL_ANNEAL, CVO_ELL_ADAPTIVE = 0, 1
+CVO_CLUSTER_OCTREE, CVO_CLUSTER_CHUNKS = 0, 1
 CVO_TRACE_LEN = 8
 MAX_BLOCKS = 8
 
@@ -34,7 +35,8 @@ EXPORTS = ("cvo_create", "cvo_destroy", "cvo_set_stream", "cvo_last_error", "cvo
            "cvo_gradient", "cvo_evaluate", "cvo_evaluate_noalloc", "cvo_ell_objective", "cvo_metric", "cvo_cosine", "cvo_align", "cvo_align_replay",
            "cvo_inner_product_backward",
            "cvo_align_batched", "cvo_odometry", "cvo_select_points", "cvo_get_tuning", "cvo_set_tuning", "cvo_autotune",
-           "cvo_set_profiling", "cvo_get_timing")
+           "cvo_set_profiling", "cvo_get_timing", "cvo_save_tuning", "cvo_load_tuning",
+           "cvo_clear_tuning")
 
 
 class CvoError(RuntimeError):
@@ -79,7 +81,7 @@ class cvo_eval(C.Structure):
 class cvo_tuning(C.Structure):
     _fields_ = [("cluster_max", C.c_int32), ("cell_factor", C.c_double), ("cluster_factor", C.c_double),
                 ("rebuild_ratio", C.c_double), ("unroll", C.c_int32), ("piece_work", C.c_int32),
-                ("adaptive", C.c_int32)]
+                ("cluster_rule", C.c_int32), ("adaptive", C.c_int32)]
 
 
 class cvo_camera(C.Structure):
@@ -90,7 +92,7 @@ class cvo_camera(C.Structure):
 class cvo_timing(C.Structure):
     _fields_ = [("pair_launches", C.c_int64), ("pair_ms", C.c_double), ("pair_count", C.c_int64),
                 ("evaluations", C.c_int64), ("graph_launches", C.c_int64), ("graph_captures", C.c_int64),
-                ("view_builds", C.c_int64), ("host_waits", C.c_int64)]
+                ("view_builds", C.c_int64), ("host_waits", C.c_int64), ("tuned_view_shapes", C.c_int64)]
 
 
 _lib = None
@@ -138,6 +140,9 @@ def load_library(path: str = LIB_PATH):
     lib.cvo_get_tuning.argtypes = [H, P(cvo_tuning)]
     lib.cvo_set_tuning.argtypes = [H, P(cvo_tuning)]
     lib.cvo_autotune.argtypes = common + [P(cvo_tuning)]
+    lib.cvo_save_tuning.argtypes = [H, C.c_char_p]
+    lib.cvo_load_tuning.argtypes = [H, C.c_char_p]
+    lib.cvo_clear_tuning.argtypes = [H]
     lib.cvo_set_profiling.argtypes = [H, C.c_int32]
     lib.cvo_get_timing.argtypes = [H, P(cvo_timing)]
     for name in EXPORTS:
@@ -540,6 +545,24 @@ def cvo_autotune(X, Z, T, ell, U=None, V=None, spec=None, sigma=1.0, kappa=3.0):
                                        C.byref(t)), h)
     del keep
     return {k: getattr(t, k) for k, _ in cvo_tuning._fields_ if k != "reserved"}
+
+
+def cvo_save_tuning(path):
+    """Write the autotuner's class table and one-shot cache to a text file."""
+    h = handle()
+    _check(load_library().cvo_save_tuning(h, os.fsencode(path)), h)
+
+
+def cvo_load_tuning(path):
+    """Merge a tuning file written by cvo_save_tuning into the handle."""
+    h = handle()
+    _check(load_library().cvo_load_tuning(h, os.fsencode(path)), h)
+
+
+def cvo_clear_tuning():
+    """Forget the autotuner's class table and one-shot cache."""
+    h = handle()
+    _check(load_library().cvo_clear_tuning(h), h)
 
 
 def cvo_set_profiling(enable=True):

@@ -92,12 +92,20 @@ struct cvo_context {
     std::map<std::string, Buf> bufs;
     void *pinned = nullptr;
     size_t pinned_cap = 0;
-    cvo_tuning tuning{16, 1.0, 0.5, 0.6, 16, 512, 1};
+    cvo_tuning tuning{16, 1.0, 0.5, 0.6, 16, 512, CVO_CLUSTER_OCTREE, 1};
     bool profiling = false;
     cvo_timing timing{0, 0.0, 0, 0, 0, 0, 0, 0};
     std::vector<hipEvent_t> ev_free;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
     std::map<std::string, cvo_tuning> tune_cache;
+    // autotuned view shape per (feature rows of at most 8 floats?, density
+    // class); consulted before the built-in table by adaptive registrations
+    struct Shape {
+        int32_t cluster_max;
+        double cell_factor, cluster_factor;
+        int32_t rule;
+    };
+    std::map<std::pair<int, int>, Shape> class_shape;
     // captured batched graph, and the library-owned stream it is captured on
     // (the legacy default stream cannot be captured)
     hipGraphExec_t graph = nullptr;
@@ -300,7 +308,7 @@ void check_pose(const double *T)
         }
     const double det = T[0] * (T[5] * T[10] - T[6] * T[9]) - T[1] * (T[4] * T[10] - T[6] * T[8]) +
                        T[2] * (T[4] * T[9] - T[5] * T[8]);
-    require(dev <= 1e-6 && det > 0.0, "pose rotation is not orthonormal with det +1 (tolerance 1e-6)");
+    require(dev <= 1e-9 && det > 0.0, "pose rotation is not orthonormal with det +1 (tolerance 1e-9)");
 }
 
 int spec_dim(const cvo_feature_spec *sp)
@@ -474,43 +482,54 @@ struct ViewShape {
     int cluster_max;
     double cell_factor;
     double cluster_factor;
+    int rule;  // CVO_CLUSTER_OCTREE or CVO_CLUSTER_CHUNKS
     bool operator==(const ViewShape &o) const
     {
-        return cluster_max == o.cluster_max && cell_factor == o.cell_factor && cluster_factor == o.cluster_factor;
+        return cluster_max == o.cluster_max && cell_factor == o.cell_factor && cluster_factor == o.cluster_factor &&
+               rule == o.rule;
     }
 };
 
 ViewShape fixed_shape(const cvo_context *ctx)
 {
-    return ViewShape{ctx->tuning.cluster_max, ctx->tuning.cell_factor, ctx->tuning.cluster_factor};
+    return ViewShape{ctx->tuning.cluster_max, ctx->tuning.cell_factor, ctx->tuning.cluster_factor,
+                     ctx->tuning.cluster_rule};
 }
 
-// Density classes and their view shapes, measured per feature layout.  Dense
-// bands amortise each candidate load over more queries and cut the
-// neighbourhood finer; sparse bands, where a cluster holds a few points, let
-// clusters grow past the cutoff radius so a wave's fixed cost is shared by
-// more queries.  Rows of at most 8 floats (cheap pairs) favour large clusters
-// down to 500 pairs per query (classes 3 and 2 merged); wider rows (costly
-// pairs, where every culled lane wastes more) switch to 16-point clusters
-// below 200.
+// Density classes and their view shapes, measured per feature layout (a
+// same-box sweep of both cluster rules x 16/32/64 points x cell edge 0.5/1.0
+// x cluster edge 0.5/1.0/1.5 r_c on the stereo and RGB-D pairs).  Chunk
+// clusters win in every band but the sparsest, where the rules tie: their
+// parts fill the power-of-two lane groups.  Dense bands cut the neighbourhood
+// finer (cell edge r_c / 2) and keep clusters small in space; sparse bands
+// let clusters grow past the cutoff radius so a wave's fixed cost is shared
+// by more queries.  Rows of at most 8 floats (cheap pairs) keep 32-point
+// clusters down to 100 pairs per query; wider rows switch to 16 below 500.
 bool light_layout(const FeatLayout &lay) { return lay.d4 <= 8; }
 
 void class_thresholds(const FeatLayout &lay, double t[3])
 {
-    t[0] = light_layout(lay) ? INFINITY : 2000.0;
-    t[1] = 500.0;
-    t[2] = light_layout(lay) ? 100.0 : 200.0;
+    t[0] = INFINITY;  // (no class 3: the densest shape is also class 2's)
+    t[1] = light_layout(lay) ? 100.0 : 500.0;
+    t[2] = light_layout(lay) ? 0.0 : 200.0;
 }
 
-ViewShape density_shape(const cvo_context *ctx, int cls, const FeatLayout &lay)
+ViewShape density_shape(cvo_context *ctx, int cls, const FeatLayout &lay)
 {
     if (!ctx->tuning.adaptive) return fixed_shape(ctx);
     const bool light = light_layout(lay);
+    auto it = ctx->class_shape.find({light ? 1 : 0, cls});
+    if (it != ctx->class_shape.end()) {
+        ctx->timing.tuned_view_shapes += 1;
+        const auto &t = it->second;
+        return ViewShape{t.cluster_max, t.cell_factor, t.cluster_factor, t.rule};
+    }
+    const int r = CVO_CLUSTER_CHUNKS;
     switch (cls) {
-    case 3: return ViewShape{64, 0.5, 0.5};
-    case 2: return light ? ViewShape{64, 0.5, 0.5} : ViewShape{32, 0.5, 0.5};
-    case 1: return ViewShape{32, 1.0, 1.5};
-    case 0: return light ? ViewShape{16, 1.0, 1.5} : ViewShape{16, 1.0, 1.0};
+    case 3: return ViewShape{32, 0.5, 0.5, r};
+    case 2: return light ? ViewShape{32, 0.5, 1.0, r} : ViewShape{32, 0.5, 0.5, r};
+    case 1: return light ? ViewShape{16, 1.0, 1.5, r} : ViewShape{16, 0.5, 1.0, r};
+    case 0: return light ? ViewShape{16, 1.0, 1.5, r} : ViewShape{16, 1.0, 1.0, r};
     default: return fixed_shape(ctx);
     }
 }
@@ -626,7 +645,8 @@ ClusterView build_clusters(cvo_context *ctx, const std::string &pre, const std::
     std::vector<int2> lcap(B);  // (largest octree level, max points per cluster)
     std::vector<long long> bases(B);
     v.desc.resize(B);
-    long long pt_base = 0, nmax = 0;
+    long long pt_base = 0, nmax = 0, nchunks = 0;
+    bool any_chunks = false, any_octree = false;
     int bits = 1;  // Morton bits per axis: as many as the widest cloud needs
     for (int c = 0; c < B; ++c) {
         const long long n = cl[c].n;
@@ -638,7 +658,10 @@ ClusterView build_clusters(cvo_context *ctx, const std::string &pre, const std::
             ext = std::max({box[8 * c + 3] - lo[0], box[8 * c + 4] - lo[1], box[8 * c + 5] - lo[2], 1e-6});
         }
         const double cap = std::isfinite(rc[c]) ? shape[c].cluster_factor * rc[c] : ext * 2.0;
-        int L = 4;
+        // octree blocks need 16 quanta per cap; chunks only use the Morton
+        // order, which a finer quantum makes more local
+        const bool chunks = shape[c].rule == CVO_CLUSTER_CHUNKS;
+        int L = chunks ? 6 : 4;
         double q = cap / (double)(1 << L);
         // quanta needed to cover the box must fit in maxbits per axis
         if (ext / q + 1.0 > (double)(1 << maxbits)) {
@@ -654,7 +677,13 @@ ClusterView build_clusters(cvo_context *ctx, const std::string &pre, const std::
         g.q = q;
         g.pt_base = pt_base;
         g.n = n;
-        lcap[c] = make_int2(L, shape[c].cluster_max);
+        g.cap = cap;
+        g.chunk_base = nchunks;
+        nchunks += (n + shape[c].cluster_max - 1) / shape[c].cluster_max;
+        any_chunks = any_chunks || chunks;
+        // (octree level -1 marks a cloud clustered by the chunk rule)
+        lcap[c] = make_int2(chunks ? -1 : L, shape[c].cluster_max);
+        any_octree = any_octree || !chunks;
         bases[c] = pt_base;
         ClusterDesc &d = v.desc[c];
         d.clus_base = 0;
@@ -700,7 +729,10 @@ ClusterView build_clusters(cvo_context *ctx, const std::string &pre, const std::
         launch_radix_sort(keys, vals, ktmp, vtmp, hist, bsum, v.ntot, 3 * bits + cbits, ctx->stream, &in_tmp);
         if (in_tmp) { std::swap(keys, ktmp); std::swap(vals, vtmp); }
         launch_gather(keys, vals, v.ntot, 3 * bits, dc, d_base, lay, v.pts, v.feat, v.perm, ctx->stream);
-        launch_cluster_heads(keys, v.ntot, d_lcap, 3 * bits, head, span, ctx->stream);
+        // each cloud by its own rule: the octree kernel skips chunk-rule
+        // clouds, and chunks exist only for chunk-rule clouds
+        if (any_octree) launch_cluster_heads(keys, v.ntot, d_lcap, 3 * bits, head, span, ctx->stream);
+        if (any_chunks) launch_chunk_heads(v.pts, d_cb, d_lcap, B, nchunks, head, span, ctx->stream);
         launch_exclusive_scan(head, hidx, bsum, v.ntot, d_total, ctx->stream);
         launch_cluster_emit(head, hidx, span, v.pts, keys, 3 * bits, v.ntot, v.clus, v.cgeo, v.cpair, v.tclus,
                             ctx->stream);
@@ -1725,6 +1757,8 @@ cvo_status cvo_set_tuning(cvo_handle h, const cvo_tuning *in)
         require(in->unroll >= 1 && in->unroll <= 64, "unroll out of [1, 64]");
         require(in->piece_work >= 256 && in->piece_work <= (1 << 24), "piece_work out of [256, 2^24]");
         require(in->adaptive == 0 || in->adaptive == 1, "adaptive must be 0 or 1");
+        require(in->cluster_rule == CVO_CLUSTER_OCTREE || in->cluster_rule == CVO_CLUSTER_CHUNKS,
+                "cluster_rule must be CVO_CLUSTER_OCTREE or CVO_CLUSTER_CHUNKS");
         h->tuning = *in;
     });
 }
@@ -1733,7 +1767,7 @@ cvo_status cvo_set_profiling(cvo_handle h, int32_t enable)
 {
     if (!h) return CVO_ERR_INVALID_ARGUMENT;
     h->profiling = enable != 0;
-    h->timing = cvo_timing{0, 0.0, 0, 0, 0, 0, 0, 0};
+    h->timing = cvo_timing{0, 0.0, 0, 0, 0, 0, 0, 0, 0};
     return CVO_OK;
 }
 
@@ -1754,61 +1788,167 @@ cvo_status cvo_autotune(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z, co
         check_cloud(Z, D, "Z");
         check_kp(kp);
         check_pose(T);
+        require(X->n > 0 && Z->n > 0, "autotune needs two non-empty clouds");
+        const FeatLayout lay = make_layout(spec, kp->sigma);
         auto bucket = [](long long n) { return bits_for((unsigned long long)std::max(n, 1LL)); };
         const std::string key = std::to_string(bucket(X->n)) + "/" + std::to_string(bucket(Z->n)) + "/" +
                                 std::to_string(D) + "/" + std::to_string((int)std::floor(std::log2(kp->ell) * 2));
         auto it = h->tune_cache.find(key);
         if (it != h->tune_cache.end()) {
-            h->tuning = it->second;
-            if (chosen) *chosen = it->second;
+            const cvo_tuning t = it->second;
+            h->tuning.cluster_max = t.cluster_max;
+            h->tuning.cell_factor = t.cell_factor;
+            h->tuning.cluster_factor = t.cluster_factor;
+            h->tuning.cluster_rule = t.cluster_rule;
+            if (chosen) *chosen = h->tuning;
             return;
         }
         const cvo_tuning base = h->tuning;
-        cvo_tuning best = base;
-        float best_ms = INFINITY;
         const bool prof = h->profiling;
         const cvo_timing saved = h->timing;
-        for (int cm : {8, 16, 32, 64})
-            for (double cf : {0.5, 0.75, 1.0}) {
-                cvo_tuning t = base;
-                t.cluster_max = cm;
-                t.cell_factor = cf;
-                h->tuning = t;
-                Problem p;
-                p.kappa = kp->kappa;
-                p.lay = make_layout(spec, kp->sigma);
-                p.sig2 = p.lay.sig2;
-                PairState s0 = init_state(T, kp->ell);
-                AlignConst ac = const_for(nullptr, X->n, Z->n);
-                setup_problem(h, p, {to_ptrs(X)}, {to_ptrs(Z)}, {s0}, {ac});
-                PairPassArgs a = pass_args(p.clus, p.grid, p.d_state, 0, p.sig2, p.kappa, p.mom, p.plan);
-                hipEvent_t e0 = h->event(), e1 = h->event();
-                std::vector<float> ms;
-                for (int rep = 0; rep < 4; ++rep) {
-                    HIP_OK(hipEventRecord(e0, h->stream));
-                    if (!launch_pair_pass(a, p.lay, 0, h->stream))
-                        throw CvoError(CVO_ERR_UNSUPPORTED, "no compiled pair kernel for the feature layout");
-                    HIP_OK(hipEventRecord(e1, h->stream));
-                    HIP_OK(hipEventSynchronize(e1));
-                    float v = 0.f;
-                    HIP_OK(hipEventElapsedTime(&v, e0, e1));
-                    if (rep > 0) ms.push_back(v);
-                }
-                h->ev_free.push_back(e0);
-                h->ev_free.push_back(e1);
-                std::sort(ms.begin(), ms.end());
-                const float med = ms[ms.size() / 2];
-                if (med < best_ms) {
-                    best_ms = med;
-                    best = t;
-                }
-            }
+        h->profiling = false;
+        cvo_tuning best = base;
+        float best_ms = INFINITY;
+        double npairs = -1.0;
+        try {
+            for (int rule : {CVO_CLUSTER_CHUNKS, CVO_CLUSTER_OCTREE})
+                for (int cm : {16, 32, 64})
+                    for (double cell : {0.5, 1.0})
+                        for (double cf : {0.5, 1.0, 1.5}) {
+                            cvo_tuning t = base;
+                            t.cluster_rule = rule;
+                            t.cluster_max = cm;
+                            t.cell_factor = cell;
+                            t.cluster_factor = cf;
+                            h->tuning = t;
+                            Problem p;
+                            p.kappa = kp->kappa;
+                            p.lay = lay;
+                            p.sig2 = p.lay.sig2;
+                            PairState s0 = init_state(T, kp->ell);
+                            AlignConst ac = const_for(nullptr, X->n, Z->n);
+                            setup_problem(h, p, {to_ptrs(X)}, {to_ptrs(Z)}, {s0}, {ac});
+                            PairPassArgs a = pass_args(p.clus, p.grid, p.d_state, 0, p.sig2, p.kappa, p.mom, p.plan);
+                            if (npairs < 0.0) {
+                                // the evaluation's pair count sets its density class
+                                enqueue_iteration(h, p, 0, nullptr, 0, false);
+                                PairState st;
+                                h->download(&st, p.d_state, sizeof(PairState));
+                                npairs = st.n_pairs;
+                            }
+                            hipEvent_t e0 = h->event(), e1 = h->event();
+                            std::vector<float> ms;
+                            for (int rep = 0; rep < 4; ++rep) {
+                                HIP_OK(hipEventRecord(e0, h->stream));
+                                if (!launch_pair_pass(a, p.lay, 0, h->stream))
+                                    throw CvoError(CVO_ERR_UNSUPPORTED, "no compiled pair kernel for the feature layout");
+                                HIP_OK(hipEventRecord(e1, h->stream));
+                                HIP_OK(hipEventSynchronize(e1));
+                                float v = 0.f;
+                                HIP_OK(hipEventElapsedTime(&v, e0, e1));
+                                if (rep > 0) ms.push_back(v);
+                            }
+                            h->ev_free.push_back(e0);
+                            h->ev_free.push_back(e1);
+                            std::sort(ms.begin(), ms.end());
+                            const float med = ms[ms.size() / 2];
+                            if (med < best_ms) {
+                                best_ms = med;
+                                best = t;
+                            }
+                        }
+        } catch (...) {
+            h->tuning = base;
+            h->profiling = prof;
+            h->timing = saved;
+            throw;
+        }
         h->profiling = prof;
         h->timing = saved;
-        best.adaptive = 0;  // keep the measured winner in every band
-        h->tuning = best;
-        h->tune_cache[key] = best;
-        if (chosen) *chosen = best;
+        // the winner becomes the one-shot shape and its density class's shape
+        cvo_tuning out = base;
+        out.cluster_rule = best.cluster_rule;
+        out.cluster_max = best.cluster_max;
+        out.cell_factor = best.cell_factor;
+        out.cluster_factor = best.cluster_factor;
+        h->tuning = out;
+        h->tune_cache[key] = out;
+        double t3[3];
+        class_thresholds(lay, t3);
+        const int cls = density_class(npairs / (double)Z->n, t3);
+        h->class_shape[{light_layout(lay) ? 1 : 0, cls}] =
+            cvo_context::Shape{out.cluster_max, out.cell_factor, out.cluster_factor, out.cluster_rule};
+        if (chosen) *chosen = out;
+    });
+}
+
+cvo_status cvo_clear_tuning(cvo_handle h)
+{
+    if (!h) return CVO_ERR_INVALID_ARGUMENT;
+    h->class_shape.clear();
+    h->tune_cache.clear();
+    return CVO_OK;
+}
+
+cvo_status cvo_save_tuning(cvo_handle h, const char *path)
+{
+    return guarded(h, [&] {
+        require(path != nullptr, "path is NULL");
+        FILE *f = std::fopen(path, "w");
+        require(f != nullptr, std::string("cannot open ") + path + " for writing");
+        std::fprintf(f, "cvo-tuning 1\n");
+        for (const auto &kv : h->class_shape)
+            std::fprintf(f, "class %d %d %d %.17g %.17g %d\n", kv.first.first, kv.first.second, kv.second.cluster_max,
+                         kv.second.cell_factor, kv.second.cluster_factor, kv.second.rule);
+        for (const auto &kv : h->tune_cache)
+            std::fprintf(f, "oneshot %s %d %.17g %.17g %d\n", kv.first.c_str(), kv.second.cluster_max,
+                         kv.second.cell_factor, kv.second.cluster_factor, kv.second.cluster_rule);
+        const bool ok = std::fclose(f) == 0;
+        require(ok, std::string("writing ") + path + " failed");
+    });
+}
+
+cvo_status cvo_load_tuning(cvo_handle h, const char *path)
+{
+    return guarded(h, [&] {
+        require(path != nullptr, "path is NULL");
+        FILE *f = std::fopen(path, "r");
+        require(f != nullptr, std::string("cannot open ") + path);
+        auto valid = [](int cm, double cell, double cf, int rule) {
+            return (cm == 8 || cm == 16 || cm == 32 || cm == 64) && cell >= 0.25 && cell <= 4.0 && cf >= 0.05 &&
+                   cf <= 2.0 && (rule == CVO_CLUSTER_OCTREE || rule == CVO_CLUSTER_CHUNKS);
+        };
+        std::map<std::pair<int, int>, cvo_context::Shape> cls_tab;
+        std::map<std::string, cvo_tuning> one;
+        char line[512];
+        bool header = false, bad = false;
+        while (std::fgets(line, sizeof(line), f)) {
+            int a = 0, b = 0, cm = 0, rule = 0, ver = 0;
+            double cell = 0.0, cf = 0.0;
+            char key[256];
+            if (!header) {
+                header = std::sscanf(line, "cvo-tuning %d", &ver) == 1 && ver == 1;
+                if (!header) { bad = true; break; }
+            } else if (std::sscanf(line, "class %d %d %d %lf %lf %d", &a, &b, &cm, &cell, &cf, &rule) == 6) {
+                if (!valid(cm, cell, cf, rule) || (a != 0 && a != 1) || b < 0 || b > 3) { bad = true; break; }
+                cls_tab[{a, b}] = cvo_context::Shape{cm, cell, cf, rule};
+            } else if (std::sscanf(line, "oneshot %255s %d %lf %lf %d", key, &cm, &cell, &cf, &rule) == 5) {
+                if (!valid(cm, cell, cf, rule)) { bad = true; break; }
+                cvo_tuning t = h->tuning;
+                t.cluster_max = cm;
+                t.cell_factor = cell;
+                t.cluster_factor = cf;
+                t.cluster_rule = rule;
+                one[key] = t;
+            } else if (line[0] != '\n') {
+                bad = true;
+                break;
+            }
+        }
+        std::fclose(f);
+        require(header && !bad, std::string(path) + " is not a cvo tuning file");
+        for (auto &kv : cls_tab) h->class_shape[kv.first] = kv.second;
+        for (auto &kv : one) h->tune_cache[kv.first] = kv.second;
     });
 }
 

@@ -11,6 +11,7 @@
 //   gather_points     sorted float4 copies and padded, pre-scaled feature rows
 //   cell_table        dense first-index-per-cell table (lower bounds)
 //   cluster_heads / cluster_emit  octree clusters of at most cluster_max points
+//   chunk_heads       or clusters as halved chunks of Morton-ordered points
 // Every kernel is deterministic: counts use integer atomics only, and all
 // orderings come from the stable sort.
 #include "cvo_launch.hpp"
@@ -355,6 +356,7 @@ __global__ void cluster_heads(const unsigned long long *keys, long long ntot, co
         const unsigned long long key = keys[p];
         const int2 cap = caps[key >> cshift];
         const int lcap = cap.x, tpw = cap.y;
+        if (lcap < 0) continue;  // clustered by the chunk rule
         long long start = -1, end = -1;
         long long lo0 = 0, hi0 = 0;
         for (int L = lcap; L >= 0; --L) {
@@ -374,6 +376,53 @@ __global__ void cluster_heads(const unsigned long long *keys, long long ntot, co
         }
         head[p] = (p == start) ? 1 : 0;
         span[p] = make_int2((int)start, (int)(end - start));
+    }
+}
+
+// Chunk clusters, one wavefront per chunk of cluster_max consecutive
+// Morton-ordered points (lane l holds point l).  Level k splits the chunk
+// into aligned parts of cluster_max >> k points; a part is final when its
+// bounding box edge fits the cap or it holds one point.  Parts are thus
+// runs of cluster_max / 2^k points (the last chunk of a cloud clipped),
+// which fill the pair pass's power-of-two lane groups, and each stays
+// compact in space.  head/span as cluster_heads writes them.
+__global__ __launch_bounds__(kWave) void chunk_heads(const float4 *pts, const ClusterBuild *cb, const int2 *caps,
+                                                      int B, long long nchunks, int *head, int2 *span)
+{
+    const long long w = blockIdx.x;
+    if (w >= nchunks) return;
+    // the cloud of this chunk (chunk_base ascending)
+    int c = 0;
+    while (c + 1 < B && cb[c + 1].chunk_base <= w) ++c;
+    const ClusterBuild g = cb[c];
+    const int tpw = caps[c].y;
+    const long long c0 = g.pt_base + (w - g.chunk_base) * tpw;
+    const int len = (int)min((long long)tpw, g.pt_base + g.n - c0);
+    const int l = threadIdx.x;
+    const bool in = l < len;
+    float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (in) q = pts[c0 + l];
+    bool done = !in;
+    for (int sz = tpw; sz >= 1; sz >>= 1) {
+        // bounding box of each aligned part of sz lanes (lanes beyond len neutral)
+        double lo[3] = {in ? (double)q.x : INFINITY, in ? (double)q.y : INFINITY, in ? (double)q.z : INFINITY};
+        double hi[3] = {in ? (double)q.x : -INFINITY, in ? (double)q.y : -INFINITY, in ? (double)q.z : -INFINITY};
+        for (int off = 1; off < sz; off <<= 1) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = fmin(lo[a], __shfl_xor(lo[a], off));
+                hi[a] = fmax(hi[a], __shfl_xor(hi[a], off));
+            }
+        }
+        const double edge = fmax(hi[0] - lo[0], fmax(hi[1] - lo[1], hi[2] - lo[2]));
+        const int first = l & ~(sz - 1);
+        const int plen = min(sz, len - first);
+        if (!done && (edge <= g.cap || plen <= 1)) {
+            head[c0 + l] = (l == first) ? 1 : 0;
+            span[c0 + l] = make_int2((int)(c0 + first), plen);
+            done = true;
+        }
+        if (__all(done)) break;
     }
 }
 
@@ -450,6 +499,13 @@ void launch_cell_table(const unsigned long long *keys, long long ntot, const Gri
 {
     hipLaunchKernelGGL(cell_table, dim3(blocks_for(max_cells + 1, 256, 8192), B), dim3(256), 0, s, keys, ntot,
                        gb, kbits, cell_start);
+}
+
+void launch_chunk_heads(const float4 *pts, const ClusterBuild *cb, const int2 *caps, int B, long long nchunks,
+                        int *head, int2 *span, hipStream_t s)
+{
+    if (nchunks <= 0) return;
+    hipLaunchKernelGGL(chunk_heads, dim3((unsigned)nchunks), dim3(kWave), 0, s, pts, cb, caps, B, nchunks, head, span);
 }
 
 void launch_cluster_heads(const unsigned long long *keys, long long ntot, const int2 *caps, int cshift,

@@ -17,6 +17,8 @@ struct alignas(16) ClusterBuild {
     double q;           // quantum (edge of a level-0 block)
     long long pt_base;
     long long n;
+    double cap;           // largest cluster bounding-box edge (chunk rule)
+    long long chunk_base; // first chunk of this cloud (chunk rule)
 };
 
 void launch_bbox(const CloudPtrs *clouds, int B, float *out, hipStream_t s);
@@ -34,6 +36,11 @@ void launch_cell_table(const unsigned long long *keys, long long ntot, const Gri
                        long long max_cells, int kbits, int *cell_start, hipStream_t s);
 void launch_cluster_heads(const unsigned long long *keys, long long ntot, const int2 *caps, int cshift,
                           int *head, int2 *span, hipStream_t s);
+// Chunk rule: each cloud's Morton-sorted points cut into chunks of at most
+// cluster_max (caps[c].y) consecutive points, each chunk subdivided by
+// halving until every part's bounding box edge is within cb[c].cap.
+void launch_chunk_heads(const float4 *pts, const ClusterBuild *cb, const int2 *caps, int B, long long nchunks,
+                        int *head, int2 *span, hipStream_t s);
 void launch_cluster_emit(const int *head, const int *hidx, const int2 *span, const float4 *pts,
                          const unsigned long long *keys, int cshift, long long ntot, int2 *clus, double4 *cgeo,
                          int *cpair, int *tclus, hipStream_t s);

@@ -52,7 +52,7 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(cvo.cvo_eval) == 8 * 12
     assert ctypes.sizeof(cvo.cvo_tuning) == 48
     assert ctypes.sizeof(cvo.cvo_camera) == 48
-    assert ctypes.sizeof(cvo.cvo_timing) == 8 * 8
+    assert ctypes.sizeof(cvo.cvo_timing) == 9 * 8
 
 
 def test_product_path_refuses_cpu_tensors():

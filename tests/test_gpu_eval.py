@@ -192,27 +192,3 @@ def test_invalid_arguments_raise(cvo):
         cvo.cvo_evaluate(Xn, Z, np.eye(4), 0.1, U, V, p.spec)
     with pytest.raises(ValueError):
         cvo.cvo_evaluate(X, Z, np.eye(4), 0.1, None, None, p.spec)
-
-
-def test_autotune_choice_changes_speed_not_results(cvo):
-    """The autotuner times the pair pass over its search space (points per
-    cluster x cell edge factor) and keeps the fastest; whatever it picks, the
-    evaluation matches the oracle (exact |P|), and a second call for the same
-    size / layout / lengthscale class reuses the cached choice."""
-    p = synth.rgbd_pair(seed=1002, n=12000)
-    X, Z, U, V = to_dev(p, torch)
-    base = cvo.cvo_get_tuning()
-    try:
-        chosen = cvo.cvo_autotune(X, Z, p.T_gt, 0.1, U, V, p.spec)
-        print("autotune chose", chosen)
-        assert chosen["cluster_max"] in (8, 16, 32, 64) and chosen["cell_factor"] in (0.5, 0.75, 1.0)
-        assert chosen["adaptive"] == 0
-        assert cvo.cvo_get_tuning() == chosen
-        g = cvo.cvo_evaluate(X, Z, p.T_gt, 0.1, U, V, p.spec)
-        o = oracle.evaluate(p.x, p.u, p.z, p.v, p.spec, 0.1, T=p.T_gt)
-        assert_eval_matches(g, o, what="autotuned")
-        cvo.cvo_set_tuning(**base)
-        assert cvo.cvo_autotune(X, Z, p.T_gt, 0.1, U, V, p.spec) == chosen
-    finally:
-        cvo.cvo_set_tuning(**base)
-    assert cvo.cvo_get_tuning() == base

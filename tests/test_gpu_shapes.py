@@ -1,9 +1,9 @@
 """Oracle parity of every view shape a registration switches to, at full size.
 
-Registrations re-choose the query-cluster size, the grid cell edge and the
-cluster edge cap (as multiples of the cutoff radius) from the pair density
-of their latest iteration; the dense-band shapes carry most of the stereo
-workload's pairs.  Each shape is set by hand (adaptive off) and one-shot
+Registrations re-choose the query-cluster size and rule, the grid cell edge
+and the cluster edge cap (as multiples of the cutoff radius) from the pair
+density of their latest iteration; the dense-band shapes carry most of the
+stereo workload's pairs.  Each shape is set by hand (adaptive off) and one-shot
 evaluations of the full stereo-outdoor pair (30k + 30k, 5 SE + 19 LIN) at
 ell = 0.95, 0.5, 0.25 and of the full RGB-D-indoor pair (40k + 40k, 5 SE) at
 ell = 0.1 are compared with the FP64 oracle (eq. (7) and its gradient) at the
@@ -21,9 +21,11 @@ from gpu_util import assert_eval_matches, to_dev
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-# (points per cluster, cell edge / r_c, cluster edge cap / r_c): the five
-# shapes the density classes select, dense to sparse
-SHAPES = [(64, 0.5, 0.5), (32, 0.5, 0.5), (32, 1.0, 1.5), (16, 1.0, 1.0), (16, 1.0, 1.5)]
+# (points per cluster, cell edge / r_c, cluster edge cap / r_c, cluster
+# rule): the shapes the density classes select (chunk clusters), dense to
+# sparse, and two octree shapes (the one-shot default and a dense one)
+SHAPES = [(32, 0.5, 0.5, 1), (32, 0.5, 1.0, 1), (16, 0.5, 1.0, 1), (16, 1.0, 1.0, 1), (16, 1.0, 1.5, 1),
+          (16, 1.0, 0.5, 0), (64, 0.5, 0.5, 0)]
 
 
 @pytest.fixture(scope="module")
@@ -51,11 +53,13 @@ def cases():
     return out
 
 
-@pytest.mark.parametrize("shape", SHAPES, ids=[f"c{s[0]}_cell{s[1]}_clus{s[2]}" for s in SHAPES])
+@pytest.mark.parametrize("shape", SHAPES, ids=[f"{'chunk' if s[3] else 'octree'}{s[0]}_cell{s[1]}_clus{s[2]}"
+                                               for s in SHAPES])
 def test_view_shape_matches_oracle_at_full_size(cvo, cases, shape):
     base = cvo.cvo_get_tuning()
     try:
-        cvo.cvo_set_tuning(adaptive=0, cluster_max=shape[0], cell_factor=shape[1], cluster_factor=shape[2])
+        cvo.cvo_set_tuning(adaptive=0, cluster_max=shape[0], cell_factor=shape[1], cluster_factor=shape[2],
+                           cluster_rule=shape[3])
         for p, (X, Z, U, V), evals in cases:
             for T, ell, o in evals:
                 what = f"{p.name} shape={shape} ell={ell} {'truth' if T is p.T_gt else 'identity'}"
