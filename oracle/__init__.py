@@ -95,6 +95,9 @@ def _load():
         lib.oracle_source_grad.argtypes = [P(_Cloud), P(_Cloud), P(_Spec), C.c_double, C.c_double,
                                            C.c_double, C.c_void_p, C.c_void_p, C.c_int64,
                                            C.c_void_p, C.c_void_p]
+        lib.oracle_target_grad.argtypes = [P(_Cloud), P(_Cloud), P(_Spec), C.c_double, C.c_double,
+                                           C.c_double, C.c_void_p, C.c_void_p, C.c_int64,
+                                           C.c_void_p, C.c_void_p]
         lib.oracle_num_threads.restype = C.c_int
         _lib = lib
     return _lib
@@ -323,3 +326,18 @@ def source_grad(x, u, z, v, spec, ell, idx, T=None, sigma=1.0, kappa=3.0):
     if rc:
         raise ValueError(f"oracle_source_grad failed ({rc})")
     return dx, du[:, :p.D]
+
+
+def target_grad(x, u, z, v, spec, ell, idx, T=None, sigma=1.0, kappa=3.0):
+    """dF/dz_j and dF/dv_j for the targets j in idx only."""
+    p = _Pair(x, u, z, v, spec)
+    T = _pose(np.eye(4) if T is None else T)
+    idx = np.ascontiguousarray(np.asarray(idx, np.int64))
+    k = idx.shape[0]
+    dz = np.zeros((k, 3)); dv = np.zeros((k, max(p.D, 1)))
+    rc = _load().oracle_target_grad(C.byref(p.X), C.byref(p.Z), C.byref(p.S), ell, sigma, kappa,
+                                    T.ctypes.data, idx.ctypes.data, k, dz.ctypes.data,
+                                    dv.ctypes.data)
+    if rc:
+        raise ValueError(f"oracle_target_grad failed ({rc})")
+    return dz, dv[:, :p.D]

@@ -856,3 +856,59 @@ int oracle_source_grad(const oracle_cloud *X, const oracle_cloud *Z, const oracl
     free(zt);
     return 0;
 }
+
+/* dF/dz_j and dF/dv_j for the targets j in idx only (the target side of
+ * oracle_backward, restricted to a subset so large clouds can be sampled):
+ *   dF/dz_j = R^T ell^-2 sum_i w_ij d_ij, d_ij = x_i - z'_j;
+ *   SE block b: dF/dv_j = + sum_i w_ij (u_i - v_j) / ell_b^2;
+ *   LIN block b: dF/dv_j = sum_i k_ij prod_{b' != b} c^(b') u_i.          */
+int oracle_target_grad(const oracle_cloud *X, const oracle_cloud *Z, const oracle_spec *sp,
+                       double ell, double sigma, double kappa, const double T[12],
+                       const int64_t *idx, int64_t nidx, double *dz, double *dv)
+{
+    if (!(ell > 0.0) || !(sigma > 0.0) || !(kappa > 0.0)) return -1;
+    const int D = spec_dim(sp);
+    const int64_t N = X->n;
+    const double rc2 = cutoff_sq(ell, kappa);
+    const double il2 = 1.0 / (ell * ell);
+    const double s2 = sigma * sigma;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < nidx; ++q) {
+        const int64_t j = idx[q];
+        double zt[3];
+        canonical_transform(T, Z->xyz + 3 * j, zt);
+        const float *vj = D ? Z->feat + (size_t)D * j : NULL;
+        double cb[ORACLE_MAX_BLOCKS];
+        double gz[3] = {0, 0, 0};
+        for (int k = 0; k < D; ++k) dv[(size_t)D * q + k] = 0.0;
+        for (int64_t i = 0; i < N; ++i) {
+            double d[3];
+            double s = canonical_distance(X->xyz + 3 * i, zt, d);
+            if (!(s <= rc2)) continue;
+            const float *ui = D ? X->feat + (size_t)D * i : NULL;
+            double c = feature_kernel(sp, ui, vj, cb);
+            double kg = s2 * exp(-s / (2.0 * ell * ell));
+            double w = c * kg;
+            for (int k = 0; k < 3; ++k) gz[k] += w * d[k];
+            int off = 0;
+            for (int b = 0; b < sp->nblocks; ++b) {
+                const int n = sp->dim[b];
+                if (sp->kind[b] == ORACLE_SE) {
+                    double ib = 1.0 / (sp->ell[b] * sp->ell[b]);
+                    for (int k = 0; k < n; ++k)
+                        dv[(size_t)D * q + off + k] += w * ((double)ui[off + k] - (double)vj[off + k]) * ib;
+                } else {
+                    double other = kg;
+                    for (int b2 = 0; b2 < sp->nblocks; ++b2)
+                        if (b2 != b) other *= cb[b2];
+                    for (int k = 0; k < n; ++k) dv[(size_t)D * q + off + k] += other * (double)ui[off + k];
+                }
+                off += n;
+            }
+        }
+        /* R^T (ell^-2 gz) */
+        for (int k = 0; k < 3; ++k)
+            dz[3 * q + k] = (T[k] * gz[0] + T[4 + k] * gz[1] + T[8 + k] * gz[2]) * il2;
+    }
+    return 0;
+}

@@ -97,4 +97,7 @@ int oracle_backward(const oracle_cloud *X, const oracle_cloud *Z, const oracle_s
 int oracle_source_grad(const oracle_cloud *X, const oracle_cloud *Z, const oracle_spec *sp,
                        double ell, double sigma, double kappa, const double T[12],
                        const int64_t *idx, int64_t nidx, double *dx, double *du);
+int oracle_target_grad(const oracle_cloud *X, const oracle_cloud *Z, const oracle_spec *sp,
+                       double ell, double sigma, double kappa, const double T[12],
+                       const int64_t *idx, int64_t nidx, double *dz, double *dv);
 #endif

@@ -530,6 +530,29 @@ def test_source_grad_subset_matches_full_backward():
     np.testing.assert_allclose(du, b["du"][idx], rtol=1e-12, atol=1e-14)
 
 
+def test_target_grad_subset_matches_full_backward_and_fd():
+    """The sampled target-side gradient equals the full backward's rows (two
+    blocks, one SE and one LIN, with a cutoff) and, without a cutoff, central
+    differences of F in the target's position and features."""
+    p = _small(seed=18, n=50, m=45, spec=[synth.se_block(2, 0.5), synth.lin_block(3)])
+    T = oracle.exp_se3([0.02, 0.01, -0.01, 0.01, 0.02, 0.0])
+    b = oracle.backward(p.x, p.u, p.z, p.v, p.spec, 0.12, T=T)
+    idx = [0, 6, 21, 44]
+    dz, dv = oracle.target_grad(p.x, p.u, p.z, p.v, p.spec, 0.12, idx, T=T)
+    np.testing.assert_allclose(dz, b["dz"][idx], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(dv, b["dv"][idx], rtol=1e-12, atol=1e-14)
+    q = _small(seed=19, n=12, m=10, spec=[synth.se_block(2, 0.5), synth.lin_block(3)], extent=0.2)
+    T = oracle.exp_se3([0.01, -0.02, 0.015, 0.01, 0.0, -0.01])
+    dz, dv = oracle.target_grad(q.x, q.u, q.z, q.v, q.spec, 0.2, [2, 9], T=T, kappa=INF)
+    for r, j in enumerate((2, 9)):
+        for comp in range(3):
+            fd = _fd_point(q, "z", j, comp, 0.2, T, h=2e-3)
+            assert dz[r, comp] == pytest.approx(fd, rel=2e-3, abs=2e-4 * (1 + abs(fd)))
+        for comp in range(5):
+            fd = _fd_point(q, "v", j, comp, 0.2, T, h=2e-3)
+            assert dv[r, comp] == pytest.approx(fd, rel=2e-3, abs=2e-4 * (1 + abs(fd)))
+
+
 def test_target_moments_sum_to_totals():
     p = _small(seed=17, n=60, m=55)
     T = oracle.exp_se3([0.02, 0.01, -0.01, 0.01, 0.02, 0.0])
