@@ -95,7 +95,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--batched", type=int, default=16,
+    ap.add_argument("--batched", type=int, default=64,
                     help="pairs in the batched-vs-plain comparison of the extras (64 = the full batched workload)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration) and exit")
@@ -271,16 +271,69 @@ def extras(cvo, torch, synth, dev, nbatch):
     X, Z, U, V = (torch.from_numpy(a).to(dev) for a in (q.x, q.z, q.u, q.v))
     sec, _ = timed(lambda: cvo.cvo_align(X, Z, U, V, q.spec, q.align), 5)
     ex["tiny_cube_50_iterations_ms"] = 1e3 * sec
-    # batched form vs looping the plain path
+    # adaptive lengthscale (the lengthscale as an optimisation variable):
+    # stereo from 0.95 with a floor of 0.1, RGB-D from 0.1 with a floor of 0.02
+    for name, q, prm in (("stereo", synth.stereo_pair(seed=1001), dict(ell_init=0.95, ell_min=0.1)),
+                         ("rgbd", synth.rgbd_pair(seed=1002), dict(ell_init=0.1, ell_min=0.02))):
+        X, Z, U, V = (torch.from_numpy(a).to(dev) for a in (q.x, q.z, q.u, q.v))
+        prm = dict(prm, max_iter=4000, ell_mode=cvo.CVO_ELL_ADAPTIVE)
+        sec, (T, rep, _) = timed(lambda: cvo.cvo_align(X, Z, U, V, q.spec, prm), 3)
+        E = np.linalg.inv(q.T_gt) @ T
+        ex[f"adaptive_{name}_registration_ms"] = 1e3 * sec
+        ex[f"adaptive_{name}_iterations"] = int(rep["iterations"])
+        ex[f"adaptive_{name}_final_ell"] = rep["final_ell"]
+        ex[f"adaptive_{name}_rot_err_deg"] = float(np.degrees(np.arccos(np.clip((np.trace(E[:3, :3]) - 1) / 2, -1, 1))))
+        ex[f"adaptive_{name}_trans_err_m"] = float(np.linalg.norm(E[:3, 3]))
+    # batched form vs looping the plain path, on the batched workload (64
+    # mixed pairs, N, M ~ U[2000, 60000]); first with the built-in density
+    # table, then with view shapes autotuned per density class
     pairs = synth.batched_pairs(seed=1004, batch=nbatch)
     tens = [tuple(torch.from_numpy(a).to(dev) for a in (b.x, b.z, b.u, b.v)) for b in pairs]
     prm = [b.align for b in pairs]
     spec = pairs[0].spec
-    tb, _ = timed(lambda: cvo.cvo_align_batched(tens, spec, prm), 1)
-    tp, _ = timed(lambda: [cvo.cvo_align(X, Z, U, V, spec, pr) for (X, Z, U, V), pr in zip(tens, prm)], 1)
+
+    def batched():
+        return cvo.cvo_align_batched(tens, spec, prm)
+
+    def plain():
+        return [cvo.cvo_align(X, Z, U, V, spec, pr) for (X, Z, U, V), pr in zip(tens, prm)]
+
+    def counted(fn):
+        fn()
+        torch.cuda.synchronize()
+        cvo.cvo_set_profiling(False)   # resets the counters
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        c = cvo.cvo_get_timing()
+        return sec, {k: c[k] for k in ("evaluations", "graph_launches", "graph_captures", "view_builds",
+                                       "host_waits", "tuned_view_shapes")}
+
+    cvo.cvo_clear_tuning()
+    tb, cb = counted(batched)
+    tp, cp = counted(plain)
     ex["batched_pairs"] = len(pairs)
+    ex["batched_points"] = int(sum(b.x.shape[0] + b.z.shape[0] for b in pairs))
     ex["batched_registrations_per_s"] = len(pairs) / tb
     ex["plain_loop_registrations_per_s"] = len(pairs) / tp
+    ex["batched_counts"] = cb
+    ex["plain_loop_counts"] = cp
+    # autotune the density classes on representative pairs of each shape
+    # (stereo: dense, middle and sparse lengthscales; RGB-D: 0.1 and 0.05)
+    t0 = time.perf_counter()
+    for q, ells in ((next(b for b in pairs if "stereo" in b.name), (0.95, 0.3, 0.12)),
+                    (next(b for b in pairs if "rgbd" in b.name), (0.1, 0.05))):
+        X, Z, U, V = (torch.from_numpy(a).to(dev) for a in (q.x, q.z, q.u, q.v))
+        for ell in ells:
+            cvo.cvo_autotune(X, Z, q.T_gt, ell, U, V, spec)
+    ex["autotune_s"] = time.perf_counter() - t0
+    tbt, cbt = counted(batched)
+    tpt, cpt = counted(plain)
+    ex["batched_autotuned_registrations_per_s"] = len(pairs) / tbt
+    ex["plain_loop_autotuned_registrations_per_s"] = len(pairs) / tpt
+    ex["batched_autotuned_counts"] = cbt
+    cvo.cvo_clear_tuning()
     # backward form: stereo-shaped pairs of 10k points, 32-dim LIN features
     lb = synth.learned_batch(seed=1003, batch=2)
     tot = 0.0

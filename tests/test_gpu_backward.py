@@ -79,7 +79,9 @@ def test_backward_identities_on_gpu_outputs(cvo):
 def test_learned_feature_workload(cvo):
     """8 stereo-shaped pairs of 10k points with 32-dim L2-normalised LIN
     features at T = T_gt Exp(0.5 deg, 2 cm), ell = 0.3: forward F and the
-    backward against the oracle (sampled rows at this size)."""
+    backward against the oracle -- every output in full for the first two
+    pairs; for the other six, 64 sampled rows of each of dX, dU, dZ, dV and
+    dF/dell against the oracle's pass."""
     pairs = synth.learned_batch(seed=1003, batch=8)
     rng = np.random.default_rng(0)
     for k, p in enumerate(pairs):
@@ -97,10 +99,19 @@ def test_learned_feature_workload(cvo):
             _cmp(b["dV"], ob["dv"], "dV")
             assert b["dell"] == pytest.approx(ob["dell"], rel=1e-5, abs=1e-5 * o["absF"] / p.ell)
         else:
+            o = oracle.evaluate(p.x, p.u, p.z, p.v, p.spec, p.ell, T=p.T_eval)
+            assert n == o["n_pairs"]
+            assert abs(F - o["F"]) <= 1e-5 * o["absF"]
             idx = rng.choice(p.x.shape[0], 64, replace=False)
             dx, du = oracle.source_grad(p.x, p.u, p.z, p.v, p.spec, p.ell, idx, T=p.T_eval)
             _cmp(b["dX"][idx], dx, f"dX sample {k}")
             _cmp(b["dU"][idx], du, f"dU sample {k}")
+            jdx = rng.choice(p.z.shape[0], 64, replace=False)
+            dz, dv = oracle.target_grad(p.x, p.u, p.z, p.v, p.spec, p.ell, jdx, T=p.T_eval)
+            _cmp(b["dZ"][jdx], dz, f"dZ sample {k}")
+            _cmp(b["dV"][jdx], dv, f"dV sample {k}")
+            # dF/dell = sum w s / ell^3 on the frozen set (the oracle's pass)
+            assert b["dell"] == pytest.approx(o["dF_dell"], rel=1e-5, abs=1e-5 * o["absF"] / p.ell)
 
 
 def test_autograd_function(cvo):
@@ -126,3 +137,76 @@ def test_autograd_function(cvo):
         Fm = cvo.cvo_inner_product(Xm, Z.detach(), T, 0.12, U.detach(), V.detach(), p.spec, kappa=float("inf"))[0]
         fd = (Fp - Fm) / (float(Xp[i, c]) - float(Xm[i, c]))
         assert X.grad[i, c].item() == pytest.approx(fd, rel=2e-3, abs=1e-3 * abs(fd) + 1e-4)
+
+
+def _local_terms(xq, uq, pts, feats, ell, rc2, frozen, moving_is_source, T):
+    """Sum of the LIN-kernel terms of one point against the other cloud over
+    its pair set frozen at the base position (float64)."""
+    if moving_is_source:
+        d = xq[None, :] - pts                       # pts: transformed targets
+    else:
+        zt = xq @ T[:3, :3].T + T[:3, 3]
+        d = pts - zt[None, :]                       # pts: sources
+    s = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+    return float(np.sum(np.where(frozen, (feats @ uq) * np.exp(-s / (2 * ell * ell)), 0.0)))
+
+
+def test_learned_feature_finite_differences(cvo):
+    """Central differences (h = 1e-3) on the learned-feature workload (all 8
+    pairs of 10k + 10k points, 32 LIN, ell = 0.3, cutoff 3 ell): for 24
+    random coordinates of each cloud's positions and features, the terms
+    involving the moved point are re-summed in float64 over the pair set
+    frozen at the base pose (the cutoff held fixed), and dF/dell from the
+    oracle's F at ell +- h with the cutoff radius fixed; the GPU backward
+    must agree within 1e-4 of the scale of its entries (the truncation
+    error of the difference is ~(h / ell)^2 / 6 ~ 2e-6)."""
+    pairs = synth.learned_batch(seed=1003, batch=8)
+    rng = np.random.default_rng(1)
+    h = 1e-3
+    for k, p in enumerate(pairs):
+        X, Z, U, V = to_dev(p, torch)
+        b = cvo.cvo_inner_product_backward(X, Z, p.T_eval, p.ell, 1.0, U, V, p.spec)
+        T, ell = p.T_eval, p.ell
+        rc = 3.0 * ell
+        rc2 = rc * rc
+        x = p.x.astype(np.float64); z = p.z.astype(np.float64)
+        u = p.u.astype(np.float64); v = p.v.astype(np.float64)
+        zt = oracle.transform(T, p.z)
+        gx = b["dX"].double().cpu().numpy(); gz = b["dZ"].double().cpu().numpy()
+        gu = b["dU"].double().cpu().numpy(); gv = b["dV"].double().cpu().numpy()
+        worst = 0.0
+        for side in ("source", "target"):
+            n = x.shape[0] if side == "source" else z.shape[0]
+            for i in rng.choice(n, 24, replace=False):
+                if side == "source":
+                    base, feat, pts, feats, gpos, gfeat = x[i], u[i], zt, v, gx[i], gu[i]
+                    d0 = base[None, :] - pts
+                else:
+                    base, feat, pts, feats, gpos, gfeat = z[i], v[i], x, u, gz[i], gv[i]
+                    d0 = pts - oracle.transform(T, p.z[i:i + 1])
+                s0 = (d0[:, 0] * d0[:, 0] + d0[:, 1] * d0[:, 1]) + d0[:, 2] * d0[:, 2]
+                frozen = s0 <= rc2
+                if not frozen.any():
+                    continue
+                src = side == "source"
+                c = rng.integers(0, 3)
+                e = np.zeros(3); e[c] = h
+                fd = (_local_terms(base + e, feat, pts, feats, ell, rc2, frozen, src, T) -
+                      _local_terms(base - e, feat, pts, feats, ell, rc2, frozen, src, T)) / (2 * h)
+                scale = np.max(np.abs(gx if src else gz)) + 1e-30
+                worst = max(worst, abs(gpos[c] - fd) / scale)
+                assert abs(gpos[c] - fd) <= 1e-4 * scale, (k, side, i, c, gpos[c], fd)
+                f = rng.integers(0, feat.shape[0])
+                ef = np.zeros(feat.shape[0]); ef[f] = h
+                fdf = (_local_terms(base, feat + ef, pts, feats, ell, rc2, frozen, src, T) -
+                       _local_terms(base, feat - ef, pts, feats, ell, rc2, frozen, src, T)) / (2 * h)
+                fscale = np.max(np.abs(gu if src else gv)) + 1e-30
+                assert abs(gfeat[f] - fdf) <= 1e-4 * fscale, (k, side, i, f, gfeat[f], fdf)
+        # lengthscale: the oracle's F at ell +- h with the cutoff radius fixed
+        op = oracle.evaluate(p.x, p.u, p.z, p.v, p.spec, ell + h, T=T, kappa=rc / (ell + h))
+        om = oracle.evaluate(p.x, p.u, p.z, p.v, p.spec, ell - h, T=T, kappa=rc / (ell - h))
+        o0 = oracle.evaluate(p.x, p.u, p.z, p.v, p.spec, ell, T=T)
+        if op["n_pairs"] == om["n_pairs"] == o0["n_pairs"]:
+            fd = (op["F"] - om["F"]) / (2 * h)
+            assert b["dell"] == pytest.approx(fd, rel=1e-4, abs=1e-4 * o0["absF"] / ell), (k, b["dell"], fd)
+        print(f"pair {k}: worst position FD deviation {worst:.2e} of the gradient scale", flush=True)
