@@ -99,6 +99,10 @@ def main():
                     help="pairs in the batched-vs-plain comparison of the extras (64 = the full batched workload)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration) and exit")
+    ap.add_argument("--iteration-trace", default=None,
+                    help="write the last timed registration's per-iteration trace (it, ell, F, |grad|, tau, "
+                         "i_theta, |P|, curvature) to this text file, to match per-dispatch counters to "
+                         "lengthscale bands")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the library runs on one GPU; more than one is not supported (use --gpus 1)"}))
@@ -123,9 +127,12 @@ def main():
     params = dict(p.align)
     torch.cuda.synchronize()
 
+    last_trace = []
+
     def step():
-        T, rep, _ = cvo.cvo_align(X, Z, U, V, p.spec, params)
+        T, rep, tr = cvo.cvo_align(X, Z, U, V, p.spec, params, trace=args.iteration_trace is not None)
         m = cvo.cvo_metric(X, Z, T, rep["final_ell"], U, V, p.spec)
+        last_trace[:] = [tr]
         return T, rep, m
 
     for _ in range(args.warmup):
@@ -142,6 +149,8 @@ def main():
     wall = time.perf_counter() - t0
     tim = cvo.cvo_get_timing()
     cvo.cvo_set_profiling(False)
+    if args.iteration_trace is not None and last_trace and last_trace[0] is not None:
+        np.savetxt(args.iteration_trace, last_trace[0])
 
     total_pairs = sum(r[1]["total_pairs"] for r in reps)
     # the metric call adds one more pass per step
