@@ -102,7 +102,11 @@ typedef struct {
 } cvo_cloud;
 
 /* Feature blocks l(x) = (u_1, u_2, ...) in V_1 x V_2 x ... (Sec. III-B).
- * Block b occupies dim[b] consecutive columns of feat, in block order. */
+ * Block b occupies dim[b] consecutive columns of feat, in block order.
+ * The feature kernel is the product of the blocks' kernels (eqs. (6)-(7)).
+ * Several LIN blocks are run as one block holding their tensor product
+ * (eq. (6)), so the product of the LIN widths plus the SE widths must not
+ * exceed CVO_MAX_FEATURE_DIM (else CVO_ERR_UNSUPPORTED). */
 typedef struct {
     int32_t nblocks;                 /* 0 .. CVO_MAX_BLOCKS */
     int32_t dim[CVO_MAX_BLOCKS];     /* > 0 */

@@ -333,8 +333,19 @@ void check_spec(const cvo_feature_spec *sp)
         else
             ++nlin;
     }
-    if (nlin > 1) throw CvoError(CVO_ERR_UNSUPPORTED, "at most one LIN feature block is supported");
     if (spec_dim(sp) > CVO_MAX_FEATURE_DIM) throw CvoError(CVO_ERR_UNSUPPORTED, "feature dimension above 64");
+    if (nlin > 1) {
+        // several LIN blocks run as their tensor product (eq. (6))
+        long long prod = 1;
+        int sed = 0;
+        for (int b = 0; b < sp->nblocks; ++b) {
+            if (sp->kind[b] == CVO_LIN) prod *= sp->dim[b];
+            else sed += sp->dim[b];
+        }
+        if (prod > 64 || sed + prod > CVO_MAX_FEATURE_DIM)
+            throw CvoError(CVO_ERR_UNSUPPORTED, "the tensor product of the LIN blocks has " + std::to_string(prod) +
+                                                    " columns; at most 64 (with the SE columns) are supported");
+    }
 }
 
 void check_cloud(const cvo_cloud *c, int D, const char *name)
@@ -360,8 +371,15 @@ FeatLayout make_layout(const cvo_feature_spec *sp, double sigma)
 {
     FeatLayout L;
     std::memset(&L, 0, sizeof(L));
-    int sed = 0, lind = 0;
-    for (int b = 0; b < sp->nblocks; ++b) (sp->kind[b] == CVO_SE ? sed : lind) += sp->dim[b];
+    int sed = 0, lind = 0, nlinb = 0, lprod = 1;
+    for (int b = 0; b < sp->nblocks; ++b) {
+        (sp->kind[b] == CVO_SE ? sed : lind) += sp->dim[b];
+        if (sp->kind[b] == CVO_LIN) {
+            ++nlinb;
+            lprod *= sp->dim[b];
+        }
+    }
+    if (nlinb > 1) lind = lprod;  // the tensor product of the LIN blocks (eq. (6))
     static const int S_opts[] = {0, 5, 8, 16, 32};
     static const int L_opts[] = {0, 4, 19, 32, 64};
     int bestS = -1, bestL = -1;
@@ -393,15 +411,34 @@ FeatLayout make_layout(const cvo_feature_spec *sp, double sigma)
     }
     dst = bestS;
     src = 0;
-    for (int b = 0; b < sp->nblocks; ++b) {
-        if (sp->kind[b] == CVO_LIN)
-            for (int k = 0; k < sp->dim[b]; ++k) {
-                L.col[dst] = src + k;
-                L.scale[dst] = 1.f;
-                L.gscale[dst] = 1.0;
-                ++dst;
+    if (nlinb > 1) {
+        L.nlin = nlinb;
+        int i = 0;
+        for (int b = 0; b < sp->nblocks; ++b) {
+            if (sp->kind[b] == CVO_LIN) {
+                L.lin_src[i] = src;
+                L.lin_dim[i] = sp->dim[b];
+                ++i;
             }
-        src += sp->dim[b];
+            src += sp->dim[b];
+        }
+        for (int c = 0; c < lprod; ++c) {
+            L.col[dst] = -2;
+            L.scale[dst] = 1.f;
+            L.gscale[dst] = 1.0;
+            ++dst;
+        }
+    } else {
+        for (int b = 0; b < sp->nblocks; ++b) {
+            if (sp->kind[b] == CVO_LIN)
+                for (int k = 0; k < sp->dim[b]; ++k) {
+                    L.col[dst] = src + k;
+                    L.scale[dst] = 1.f;
+                    L.gscale[dst] = 1.0;
+                    ++dst;
+                }
+            src += sp->dim[b];
+        }
     }
     L.sig2 = (float)sig2;
     return L;
@@ -1697,6 +1734,7 @@ cvo_status cvo_inner_product_backward(cvo_handle h, const cvo_cloud *X, const cv
             ba.gF = gF;
             ba.dxyz = dZ;
             ba.dfeat = dV;
+            ba.src_feat = Z->feat;
             ba.n = M;
             launch_backward_finish(ba, h->stream);
             if (dEll) {
@@ -1729,6 +1767,7 @@ cvo_status cvo_inner_product_backward(cvo_handle h, const cvo_cloud *X, const cv
             ba.gF = gF;
             ba.dxyz = dX;
             ba.dfeat = dU;
+            ba.src_feat = X->feat;
             ba.n = N;
             launch_backward_finish(ba, h->stream);
             h->check_launch("backward (source side)");

@@ -312,8 +312,21 @@ __global__ void gather_points(const unsigned long long *keys, const int *vals, l
         perm[p] = (int)i;
         if (lay.d4 > 0) {
             const float *f = clouds[c].feat + i * lay.src_dim;
-            for (int k = 0; k < lay.d4; ++k)
-                feat[p * lay.d4 + k] = (lay.col[k] >= 0) ? f[lay.col[k]] * lay.scale[k] : 0.0f;
+            for (int k = 0; k < lay.d4; ++k) {
+                float v = 0.0f;
+                if (lay.col[k] >= 0) {
+                    v = f[lay.col[k]] * lay.scale[k];
+                } else if (lay.col[k] == -2) {
+                    // tensor-product column of the folded LIN blocks (eq. (6))
+                    int cc = k - lay.sed;
+                    v = 1.0f;
+                    for (int b = lay.nlin - 1; b >= 0; --b) {
+                        v *= f[lay.lin_src[b] + cc % lay.lin_dim[b]];
+                        cc /= lay.lin_dim[b];
+                    }
+                }
+                feat[p * lay.d4 + k] = v;
+            }
         }
     }
 }

@@ -103,7 +103,16 @@ struct FeatLayout {
     int sed, lind;     // SE columns, LIN columns of the kernel variant (padded)
     int d4;            // row stride (multiple of 4, >= sed + lind)
     int src_dim;       // D of the caller's rows
-    int col[64];       // destination column -> source column (-1: zero padding)
+    // Several LIN blocks are folded into one by the tensor-product identity
+    // of eq. (6), <u1 (x) u2, v1 (x) v2> = <u1, v1> <u2, v2>: destination LIN
+    // column sed + c (c < prod lin_dim) holds prod_b u_b[digit_b(c)], the
+    // digits of c in the mixed radix (lin_dim[0], ..., lin_dim[nlin - 1])
+    // with block 0 most significant.  nlin = 0: at most one LIN block, mapped
+    // column by column through col[].
+    int nlin;
+    int lin_src[8];    // first source column of each LIN block
+    int lin_dim[8];    // its width
+    int col[64];       // destination column -> source column (-1: zero padding; -2: tensor-product column)
     float scale[64];   // destination column scale (SE: sqrt(log2(e) / (2 ell_b^2)))
     double gscale[64]; // accumulated feature gradient -> dF/d(feature) (SE: 1/(scale ell_b^2))
     float sig2;        // sigma^2 * prod_b sigma_b^2 over SE blocks

@@ -98,6 +98,8 @@ struct BackwardArgs {
     double gF;
     float *dxyz;              // original-order output, n x 3 (may be null)
     float *dfeat;             // original-order output, n x src_dim (may be null)
+    const float *src_feat;    // the query cloud's own feature rows (original order, n x src_dim), read
+                              // for the chain rule through folded LIN blocks
     long long n;
 };
 void launch_backward_finish(const BackwardArgs &a, hipStream_t s);

@@ -567,14 +567,41 @@ __global__ void backward_finish(const BackwardArgs a)
                 a.dxyz[3 * o + k] = (float)(f * (P[k] * d0 + P[4 + k] * d1 + P[8 + k] * d2));
         }
         if (a.dfeat) {
+            // folded LIN blocks: the gradient of a tensor-product column c
+            // reaches u_b[digit_b(c)] times the other blocks' factors of c
+            double gl[64];
+            if (a.lay.nlin > 0)
+                for (int k = 0; k < 64; ++k) gl[k] = 0.0;
+            const float *f = a.lay.nlin > 0 ? a.src_feat + o * a.lay.src_dim : nullptr;
             for (int k = 0; k < a.lay.d4; ++k) {
                 const int col = a.lay.col[k];
-                if (col < 0) continue;
+                if (col == -1) continue;
                 double gk = 0.0;
                 for (int i = 0; i < qm.z; ++i)
                     gk += a.G[((long long)qm.w + (long long)i * qm.y) * a.lay.d4 + k];
-                a.dfeat[o * a.lay.src_dim + col] = (float)(a.gF * gk * a.lay.gscale[k]);
+                if (col >= 0) {
+                    a.dfeat[o * a.lay.src_dim + col] = (float)(a.gF * gk * a.lay.gscale[k]);
+                } else {
+                    int dig[8];
+                    int cc = k - a.lay.sed;
+                    for (int b = a.lay.nlin - 1; b >= 0; --b) {
+                        dig[b] = cc % a.lay.lin_dim[b];
+                        cc /= a.lay.lin_dim[b];
+                    }
+                    for (int b = 0; b < a.lay.nlin; ++b) {
+                        double other = 1.0;
+                        for (int b2 = 0; b2 < a.lay.nlin; ++b2)
+                            if (b2 != b) other *= (double)f[a.lay.lin_src[b2] + dig[b2]];
+                        gl[a.lay.lin_src[b] + dig[b]] += gk * other;
+                    }
+                }
             }
+            if (a.lay.nlin > 0)
+                for (int b = 0; b < a.lay.nlin; ++b)
+                    for (int j = 0; j < a.lay.lin_dim[b]; ++j) {
+                        const int col = a.lay.lin_src[b] + j;
+                        a.dfeat[o * a.lay.src_dim + col] = (float)(a.gF * gl[col]);
+                    }
         }
     }
 }
