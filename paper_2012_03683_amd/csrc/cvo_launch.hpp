@@ -77,7 +77,7 @@ struct ReduceArgs {
     const int *cnt;
     PairState *state;
     const AlignConst *ac;
-    double *partials;          // B * nblk * kRedVals
+    double *partials;          // B * kRedVals * nblk (per pair value-major: value v of block k at v * nblk + k)
     double *trace;             // B * trace_rows * kTraceLen, may be null
     long long trace_rows;
     int nblk;

@@ -14,9 +14,10 @@
 //     box around the ball of radius r_c + rho (rho: cluster radius).  The
 //     box's x-runs of cells are contiguous in the sorted reference array; up
 //     to 64 runs are measured at once (one per lane), prefix-summed, and
-//     their points loaded 64 at a time.  Points outside the ball are culled;
-//     survivors (coordinates and feature rows) are compacted with a ballot
-//     into a per-wave LDS queue.
+//     their points loaded 64 at a time (each position finds its run by a
+//     running max over the runs' first positions).  Points outside the ball
+//     are culled; survivors (coordinates and feature rows) are compacted with
+//     a ballot into a per-wave LDS queue.
 //   * When the queue holds >= 64 entries every lane walks its share: FP32
 //     squared distance, cutoff test, one exp2 for the geometric kernel and
 //     every SE feature block together, the LIN dot product, then FP64
@@ -133,11 +134,14 @@ void pair_pass_kernel(const PairPassArgs a)
     constexpr int F4 = D4 / 4;
     constexpr int F4s = F4 > 0 ? F4 : 1;
     constexpr int VF = D4 > 0 ? D4 : 1;
-    __shared__ float4 s_xyz[kWavesPerBlock][kQueueCap];
-    __shared__ float4 s_ft[kWavesPerBlock][kQueueCap * F4s];
-    __shared__ int s_src[kWavesPerBlock][kQueueCap];
+    // candidate queue, one entry of E4 float4s per candidate: (scaled
+    // coordinates relative to the cluster centre, source index bits), then
+    // the feature row
+    constexpr int E4 = 1 + F4;
+    __shared__ float4 s_q[kWavesPerBlock][kQueueCap * E4];
     __shared__ int s_rs[kWavesPerBlock][kWave];
     __shared__ int s_rx[kWavesPerBlock][kWave];
+    __shared__ int s_row[kWavesPerBlock][kWave];
 
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
@@ -223,80 +227,101 @@ void pair_pass_kernel(const PairPassArgs a)
 
         // W and D are summed in FP32 over one queue flush (at most kQueueCap
         // terms per lane) and added to the FP64 accumulators after it.
-        auto process = [&](int qn) {
-            float w32 = 0.f, dx32 = 0.f, dy32 = 0.f, dz32 = 0.f;
-            // the next candidate's coordinates are read from LDS as soon as
-            // this one's distance is known, so the read overlaps the rest of
-            // the iteration (index clamped inside the queue)
-            float4 e = s_xyz[wv][qs];
-            for (int k = qs; k < qn; k += SUB) {
-                const float dx = e.x - zrx, dy = e.y - zry, dz = e.z - zrz;
-                const float s = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                {
-                    const int kn = k + SUB;
-                    e = s_xyz[wv][kn < kQueueCap ? kn : kQueueCap - 1];
+        float w32 = 0.f, dx32 = 0.f, dy32 = 0.f, dz32 = 0.f;
+        // one candidate entry (at `ent`; its offset d from the query and
+        // squared distance s already taken) against this lane's query;
+        // `valid` false only in the tail of a flush, for lanes past its end
+        auto pair_term = [&](float dx, float dy, float dz, float s, const float4 *ent, bool valid) {
+            if (valid && active && s <= hi) {
+                bool pass = true;
+                if (s > lo) {
+                    const float4 rp = a.rpts[__float_as_int(ent[0].w)];
+                    const float4 zq2 = a.qpts[pq];
+                    pass = a.pose_is_inverse
+                               ? canonical_member(st->T, zq2.x, zq2.y, zq2.z, rp.x, rp.y, rp.z, rc2)
+                               : canonical_member(st->T, rp.x, rp.y, rp.z, zq2.x, zq2.y, zq2.z, rc2);
                 }
-                if (active && s <= hi) {
-                    bool pass = true;
-                    if (s > lo) {
-                        const float4 rp = a.rpts[s_src[wv][k]];
-                        const float4 zq2 = a.qpts[pq];
-                        pass = a.pose_is_inverse
-                                   ? canonical_member(st->T, zq2.x, zq2.y, zq2.z, rp.x, rp.y, rp.z, rc2)
-                                   : canonical_member(st->T, rp.x, rp.y, rp.z, zq2.x, zq2.y, zq2.z, rc2);
+                if (pass) {
+                    float E = s;
+                    float lin = 0.0f, lin1 = 0.0f;  // even / odd LIN columns: two shorter FMA chains
+#pragma unroll
+                    for (int f = 0; f < F4; ++f) {
+                        const float4 u4 = ent[1 + f];
+                        const float uu[4] = {u4.x, u4.y, u4.z, u4.w};
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int d = 4 * f + q;
+                            if (d < SED) {
+                                const float df = uu[q] - vf[d];
+                                E = fmaf(df, df, E);
+                            } else if (d < D) {
+                                if ((d - SED) & 1) lin1 = fmaf(uu[q], vf[d], lin1);
+                                else lin = fmaf(uu[q], vf[d], lin);
+                            }
+                        }
                     }
-                    if (pass) {
-                        float E = s;
-                        float lin = 0.0f, lin1 = 0.0f;  // even / odd LIN columns: two shorter FMA chains
+                    lin += lin1;
+                    // sigma^2 prod sigma_b^2 is applied once per query at the end
+                    const float wnl = __builtin_amdgcn_exp2f(-E);
+                    const float w = (LIND > 0) ? wnl * lin : wnl;
+                    w32 += w;
+                    const float wx = w * dx, wy = w * dy, wz = w * dz;
+                    dx32 += wx;
+                    dy32 += wy;
+                    dz32 += wz;
+                    cnt += 1;
+                    if (MODE == 0) {
+                        S00 = fmaf(wx, dx, S00);
+                        S01 = fmaf(wx, dy, S01);
+                        S02 = fmaf(wx, dz, S02);
+                        S11 = fmaf(wy, dy, S11);
+                        S12 = fmaf(wy, dz, S12);
+                        S22 = fmaf(wz, dz, S22);
+                    } else {
+                        Ls += (double)(w * s);
 #pragma unroll
                         for (int f = 0; f < F4; ++f) {
-                            const float4 u4 = s_ft[wv][k * F4 + f];
+                            const float4 u4 = ent[1 + f];
                             const float uu[4] = {u4.x, u4.y, u4.z, u4.w};
 #pragma unroll
                             for (int q = 0; q < 4; ++q) {
                                 const int d = 4 * f + q;
-                                if (d < SED) {
-                                    const float df = uu[q] - vf[d];
-                                    E = fmaf(df, df, E);
-                                } else if (d < D) {
-                                    if ((d - SED) & 1) lin1 = fmaf(uu[q], vf[d], lin1);
-                                    else lin = fmaf(uu[q], vf[d], lin);
-                                }
-                            }
-                        }
-                        lin += lin1;
-                        // sigma^2 prod sigma_b^2 is applied once per query at the end
-                        const float wnl = __builtin_amdgcn_exp2f(-E);
-                        const float w = (LIND > 0) ? wnl * lin : wnl;
-                        w32 += w;
-                        const float wx = w * dx, wy = w * dy, wz = w * dz;
-                        dx32 += wx;
-                        dy32 += wy;
-                        dz32 += wz;
-                        cnt += 1;
-                        if (MODE == 0) {
-                            S00 = fmaf(wx, dx, S00);
-                            S01 = fmaf(wx, dy, S01);
-                            S02 = fmaf(wx, dz, S02);
-                            S11 = fmaf(wy, dy, S11);
-                            S12 = fmaf(wy, dz, S12);
-                            S22 = fmaf(wz, dz, S22);
-                        } else {
-                            Ls += (double)(w * s);
-#pragma unroll
-                            for (int f = 0; f < F4; ++f) {
-                                const float4 u4 = s_ft[wv][k * F4 + f];
-                                const float uu[4] = {u4.x, u4.y, u4.z, u4.w};
-#pragma unroll
-                                for (int q = 0; q < 4; ++q) {
-                                    const int d = 4 * f + q;
-                                    if (MODE == 1 && d < SED) Gf[d] += (double)(w * (uu[q] - vf[d]));
-                                    else if (MODE == 1 && d < D) Gf[d] += (double)(wnl * uu[q]);
-                                }
+                                if (MODE == 1 && d < SED) Gf[d] += (double)(w * (uu[q] - vf[d]));
+                                else if (MODE == 1 && d < D) Gf[d] += (double)(wnl * uu[q]);
                             }
                         }
                     }
                 }
+            }
+        };
+        // Lane (q, t) walks entries q, q + SUB, ...: first the rows of SUB
+        // entries that every sub-stream has (a wave-uniform loop, the next
+        // entry's coordinates read while this one is used), then the last,
+        // partial row.
+        auto process = [&](int qn_) {
+            w32 = 0.f, dx32 = 0.f, dy32 = 0.f, dz32 = 0.f;
+            const int qn = wave_uniform(qn_);
+            const int nfull = wave_uniform(qn >> (6 - lg));  // qn / SUB
+            const float4 *ent = &s_q[wv][qs * E4];
+            const int step = SUB * E4;
+            float4 e = ent[0];
+            for (int it = 0; it < nfull; ++it) {
+                const float dx = e.x - zrx, dy = e.y - zry, dz = e.z - zrz;
+                const float s = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                const float4 *cur = ent;
+                ent += (it + 1 < nfull) ? step : 0;  // (the last row re-reads itself)
+                e = *ent;
+                pair_term(dx, dy, dz, s, cur, true);
+            }
+            const int done = wave_uniform(nfull << (6 - lg));
+            if (done < qn) {
+                const int kt = qs + done;
+                const bool in = kt < qn;
+                const float4 *tl = &s_q[wv][(in ? kt : 0) * E4];
+                const float4 c = *tl;
+                const float dx = c.x - zrx, dy = c.y - zry, dz = c.z - zrz;
+                const float s = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                pair_term(dx, dy, dz, s, tl, in);
             }
             W += (double)w32;
             Dx += (double)dx32;
@@ -338,6 +363,7 @@ void pair_pass_kernel(const PairPassArgs a)
                 if (k * kWave < base + total) {
                     s_rs[wv][lane] = rs;
                     s_rx[wv][lane] = incl - len;
+                    s_row[wv][lane] = 0;  // marks left by earlier chunks of this batch never exceed a later chunk's rows
                     wave_sync();
                     for (; k * kWave < base + total; k += pstride) {
                         // the part of chunk k inside this batch of rows
@@ -345,13 +371,25 @@ void pair_pass_kernel(const PairPassArgs a)
                         bool keep = false;
                         int src = 0;
                         float x0 = 0.f, x1 = 0.f, x2 = 0.f;
+                        // the row (cell run) of each position of the chunk: every
+                        // non-empty row reaching into the chunk marks its first
+                        // position in it with its index, and a running max over
+                        // the positions (on all lanes, before the branch below)
+                        // fills in the rest
+                        {
+                            const int c0 = k * kWave - base;
+                            const int rx = incl - len;
+                            if (len > 0 && rx < c0 + kWave && rx + len > c0) s_row[wv][max(rx - c0, 0)] = lane;
+                        }
+                        wave_sync();
+                        int row_ = s_row[wv][lane];
+#pragma unroll
+                        for (int off = 1; off < kWave; off <<= 1) {
+                            const int v = __shfl_up(row_, off);
+                            if (lane >= off) row_ = max(row_, v);
+                        }
                         if (m >= 0 && m < total) {
-                            int lo_ = 0, hi_ = kWave - 1;
-                            while (lo_ < hi_) {
-                                const int mid = (lo_ + hi_ + 1) >> 1;
-                                if (s_rx[wv][mid] <= m) lo_ = mid; else hi_ = mid - 1;
-                            }
-                            src = s_rs[wv][lo_] + (m - s_rx[wv][lo_]);
+                            src = s_rs[wv][row_] + (m - s_rx[wv][row_]);
                             const float4 xp = a.rpts[src];
                             x0 = (float)(((double)xp.x - cx) * sc);
                             x1 = (float)(((double)xp.y - cy) * sc);
@@ -361,11 +399,10 @@ void pair_pass_kernel(const PairPassArgs a)
                         const unsigned long long mask = __ballot(keep);
                         if (keep) {
                             const int slot = qn + __popcll(mask & lt_mask);
-                            s_xyz[wv][slot] = make_float4(x0, x1, x2, 0.0f);
-                            s_src[wv][slot] = src;
+                            s_q[wv][slot * E4] = make_float4(x0, x1, x2, __int_as_float(src));
                             const float4 *fr = reinterpret_cast<const float4 *>(a.rfeat) + (long long)src * F4;
 #pragma unroll
-                            for (int f = 0; f < F4; ++f) s_ft[wv][slot * F4 + f] = fr[f];
+                            for (int f = 0; f < F4; ++f) s_q[wv][slot * E4 + 1 + f] = fr[f];
                         }
                         qn += __popcll(mask);
                         wave_sync();
@@ -586,3 +623,4 @@ bool launch_pair_pass(const PairPassArgs &a, const FeatLayout &lay, int mode, hi
 }
 
 }  // namespace cvo
+

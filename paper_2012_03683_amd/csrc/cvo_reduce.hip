@@ -447,7 +447,7 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
     constexpr int kChunk = 24, kStripes = 8;
     __shared__ double red[kChunk][kRedThreads];
     const int tid = threadIdx.x;
-    double *part = a.partials + ((long long)b * a.nblk + blockIdx.x) * kRedVals;
+    double *part = a.partials + (long long)b * a.nblk * kRedVals + blockIdx.x;  // value-major
     {
         const int kv = tid / kStripes, sl = tid % kStripes;
 #pragma unroll
@@ -468,7 +468,7 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
                     const double o = __shfl_xor(v, off);
                     v = mx ? fmax(v, o) : v + o;
                 }
-                if (sl == 0) part[kChunk * c + kv] = v;
+                if (sl == 0) part[(long long)(kChunk * c + kv) * a.nblk] = v;
             }
             __syncthreads();
         }
@@ -476,8 +476,9 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
 }
 
 // Second stage, one workgroup per pair: thread (kv = t / 32, stripe sl =
-// t % 32) adds blocks sl, sl + 32, ... of the values kv + 8 c, four stripes'
-// loads in flight at once; a 32-lane shuffle tree finishes, and one thread
+// t % 32) adds blocks sl, sl + 32, ... of the values kv + 8 c (value-major
+// partials: a wave's loads are two runs of 32 consecutive doubles), four
+// stripes' loads in flight at once; a 32-lane shuffle tree finishes, and one thread
 // finishes the pair.  Fixed order throughout.  A separate launch rather than
 // a last-block ticket: the kernel boundary makes the partials visible to
 // every XCD without a device-scope fence in each block of the first stage.
@@ -507,7 +508,7 @@ __global__ __launch_bounds__(kRedThreads) void reduce_finish_kernel(const Reduce
         for (int u = 0; u < 4; ++u) {
             const int q = q0 + 32 * u;
 #pragma unroll
-            for (int c = 0; c < R_END / 8; ++c) p[u][c] = (q < a.nblk) ? pb[(long long)q * kRedVals + 8 * c + kv] : 0.0;
+            for (int c = 0; c < R_END / 8; ++c) p[u][c] = (q < a.nblk) ? pb[(long long)(8 * c + kv) * a.nblk + q] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
