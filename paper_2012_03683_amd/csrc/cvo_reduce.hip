@@ -104,9 +104,10 @@ __device__ void exp_se3(const double xi[6], double E[12])
     double ca, cb, cc;
     if (th < 1e-2) {
         const double th4 = th2 * th2, th6 = th4 * th2;
-        ca = 1.0 - th2 / 6.0 + th4 / 120.0 - th6 / 5040.0;
-        cb = 0.5 - th2 / 24.0 + th4 / 720.0 - th6 / 40320.0;
-        cc = 1.0 / 6.0 - th2 / 120.0 + th4 / 5040.0 - th6 / 362880.0;
+        // (reciprocal factorials as constants: multiplications, not divisions)
+        ca = 1.0 - th2 * (1.0 / 6.0) + th4 * (1.0 / 120.0) - th6 * (1.0 / 5040.0);
+        cb = 0.5 - th2 * (1.0 / 24.0) + th4 * (1.0 / 720.0) - th6 * (1.0 / 40320.0);
+        cc = 1.0 / 6.0 - th2 * (1.0 / 120.0) + th4 * (1.0 / 5040.0) - th6 * (1.0 / 362880.0);
     } else {
         const double sh = sin(0.5 * th);
         ca = sin(th) / th;
@@ -162,7 +163,8 @@ __device__ __forceinline__ void finalize_local(PairState &st, const AlignConst &
                                                double *trace, long long trace_rows, int mode)
 {
     const double ell = st.ell;
-    const double il2 = 1.0 / (ell * ell);
+    const double il1 = 1.0 / ell;
+    const double il2 = il1 * il1;
     double g[6];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -177,14 +179,20 @@ __device__ __forceinline__ void finalize_local(PairState &st, const AlignConst &
     st.i_theta = ind;
     st.curv = curv;
     st.r_max = tot[R_RMAX];
-    st.dF_dell = tot[R_TRS] / (ell * ell * ell);
+    st.dF_dell = tot[R_TRS] * il2 * il1;
     st.n_pairs = np;
     {
-        // lengthscale objective J = sum log W_j - 3 |Z+| log ell (zero unless reduced)
+        // lengthscale objective J = sum log W_j - 3 |Z+| log ell (all zero
+        // unless its sums were reduced)
         const double mp = tot[R_ZP];
-        st.J = tot[R_LOGW] - 3.0 * mp * log(ell);
-        st.dJ_dell = tot[R_RSUM] / (ell * ell * ell) - 3.0 * mp / ell;
-        st.ell_ml = mp > 0.0 ? sqrt(tot[R_RSUM] / (3.0 * mp)) : 0.0;
+        st.J = 0.0;
+        st.dJ_dell = 0.0;
+        st.ell_ml = 0.0;
+        if (mp > 0.0) {
+            st.J = tot[R_LOGW] - 3.0 * mp * log(ell);
+            st.dJ_dell = tot[R_RSUM] * il2 * il1 - 3.0 * mp * il1;
+            st.ell_ml = sqrt(tot[R_RSUM] / (3.0 * mp));
+        }
         st.zplus = mp;
     }
 #pragma unroll
