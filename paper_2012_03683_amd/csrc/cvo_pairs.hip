@@ -43,6 +43,33 @@ __device__ __forceinline__ void wave_sync()
 
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Inclusive scans over the 64 lanes of a wave with DPP row shifts and row
+// broadcasts (no LDS traffic): within each row of 16 lanes a Hillis-Steele
+// scan over shifts 1, 2, 4, 8 (lanes shifted in from outside the row add
+// the identity 0), then row 0's last lane is added to row 1 and row 2's to
+// row 3, then lane 31 to rows 2 and 3.  The max scan needs values >= 0.
+__device__ __forceinline__ int wave_scan_add(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
+__device__ __forceinline__ int wave_scan_max(int v)
+{
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false));
+    return v;
+}
+
 // Wave-uniform floating values kept in scalar registers.
 __device__ __forceinline__ float uniform_f(float v)
 {
@@ -350,13 +377,8 @@ void pair_pass_kernel(const PairPassArgs a)
                     rs = a.cell_start[k0];
                     len = a.cell_start[k0 + run] - rs;
                 }
-                int incl = len;
-#pragma unroll
-                for (int off = 1; off < kWave; off <<= 1) {
-                    const int v = __shfl_up(incl, off);
-                    if (lane >= off) incl += v;
-                }
-                const int total = __shfl(incl, kWave - 1);
+                const int incl = wave_scan_add(len);
+                const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
                 // first chunk of this piece reaching into [base, base + total)
                 int k = base / kWave;
                 k += ((pidx - k) % pstride + pstride) % pstride;
@@ -382,12 +404,7 @@ void pair_pass_kernel(const PairPassArgs a)
                             if (len > 0 && rx < c0 + kWave && rx + len > c0) s_row[wv][max(rx - c0, 0)] = lane;
                         }
                         wave_sync();
-                        int row_ = s_row[wv][lane];
-#pragma unroll
-                        for (int off = 1; off < kWave; off <<= 1) {
-                            const int v = __shfl_up(row_, off);
-                            if (lane >= off) row_ = max(row_, v);
-                        }
+                        const int row_ = wave_scan_max(s_row[wv][lane]);
                         if (m >= 0 && m < total) {
                             src = s_rs[wv][row_] + (m - s_rx[wv][row_]);
                             const float4 xp = a.rpts[src];
