@@ -23,8 +23,10 @@ pytestmark = pytest.mark.gpu
 
 # (points per cluster, cell edge / r_c, cluster edge cap / r_c, cluster
 # rule): the shapes the density classes select (chunk clusters), dense to
-# sparse, and two octree shapes (the one-shot default and a dense one)
-SHAPES = [(32, 0.5, 0.5, 1), (32, 0.5, 1.0, 1), (16, 0.5, 1.0, 1), (16, 1.0, 1.0, 1), (16, 1.0, 1.5, 1),
+# sparse, two shapes of earlier class tables, and two octree shapes (the
+# one-shot default and a dense one)
+SHAPES = [(32, 0.35, 0.3, 1), (32, 0.35, 0.5, 1), (32, 0.5, 1.0, 1), (16, 0.5, 1.0, 1), (16, 1.0, 1.0, 1),
+          (16, 0.5, 1.5, 1), (32, 0.5, 0.5, 1), (16, 1.0, 1.5, 1),
           (16, 1.0, 0.5, 0), (64, 0.5, 0.5, 0),
           # the finest cells allowed: a neighbourhood spans more than 64 rows of
           # cells, so the pass measures its rows in several batches
