@@ -41,7 +41,10 @@
  *
  * Errors: every call returns a cvo_status; on failure cvo_last_error()
  * gives a message.  A pose must be rigid: max |R^T R - I| <= 1e-9 and
- * det R > 0, with finite entries (else CVO_ERR_INVALID_ARGUMENT).  N = 0 or M = 0 is not an error (F = 0, gradient 0,
+ * det R > 0, with finite entries (else CVO_ERR_INVALID_ARGUMENT).  Point
+ * coordinates must be finite: a cloud with a NaN or infinite coordinate is
+ * found on the device at the view build and rejected with
+ * CVO_ERR_INVALID_ARGUMENT.  N = 0 or M = 0 is not an error (F = 0, gradient 0,
  * |P| = 0; cvo_align reports CVO_NO_OVERLAP and returns T_init).
  * Non-convergence is a report status, never an error code.
  */
