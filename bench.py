@@ -28,6 +28,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -55,11 +56,19 @@ KERNEL_SOURCES = ("paper_2012_03683_amd/csrc/cvo_pairs.hip", "paper_2012_03683_a
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pair_pass_traffic.json")
 
 
+def _code_only(text):
+    """The source without comments, trailing blanks and empty lines, so that
+    editing a comment does not invalidate counters taken on the same code."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines())
+    return "\n".join(ln for ln in lines if ln)
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f)) as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()
 
 

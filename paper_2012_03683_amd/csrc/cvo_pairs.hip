@@ -15,13 +15,15 @@
 //     box's x-runs of cells are contiguous in the sorted reference array; up
 //     to 64 runs are measured at once (one per lane), prefix-summed, and
 //     their points loaded 64 at a time (each position finds its run by a
-//     running max over the runs' first positions).  Points outside the ball
-//     are culled; survivors (coordinates and feature rows) are compacted with
-//     a ballot into a per-wave LDS queue.
-//   * When the queue holds >= 64 entries every lane walks its share: FP32
-//     squared distance, cutoff test, one exp2 for the geometric kernel and
-//     every SE feature block together, the LIN dot product, then FP64
-//     accumulation of W = sum w and D = sum w d, FP32 S = sum w d d^T.
+//     running max over the runs' first positions; both scans use DPP, not
+//     the LDS, which the other waves' walks keep busy).  Points outside the
+//     ball are culled; survivors (coordinates and feature rows) are compacted
+//     with a ballot into a per-wave LDS queue.
+//   * When the queue holds at least kQueueFlush entries every lane walks its
+//     share: FP32 squared distance, cutoff test, one exp2 for the geometric
+//     kernel and every SE feature block together, the LIN dot product; W =
+//     sum w and D = sum w d are summed in FP32 over the flush and then added
+//     in FP64, S = sum w d d^T is summed in FP32.
 //   * Pairs whose FP32 squared distance lies within a proven error band of
 //     the cutoff are decided again with the FP64 expression that defines the
 //     pair set, so |P| is exact.
