@@ -1039,6 +1039,9 @@ void iteration_args(const Problem &p, int mode, double *trace, long long trace_r
     r.nblk = p.nblk;
     r.mode = mode;
     r.ellobj = p.ellobj;
+    long long mx = 0;
+    for (const auto &d : p.clus.desc) mx = std::max(mx, (long long)d.n);
+    r.one_query = (long long)p.nblk * kRedThreads >= mx;
 }
 
 void enqueue_iteration(cvo_context *ctx, Problem &p, int mode, double *trace, long long trace_rows, bool timed)

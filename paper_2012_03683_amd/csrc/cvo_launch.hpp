@@ -83,6 +83,7 @@ struct ReduceArgs {
     int nblk;
     int mode;                  // 0: evaluate only, 1: evaluate and take an ascent step
     int ellobj;                // nonzero: also reduce the lengthscale objective's sums
+    int one_query;             // nonzero: nblk * kRedThreads >= every cloud's query count (one query per thread)
 };
 void launch_reduce(const ReduceArgs &a, int B, hipStream_t s);
 

@@ -328,6 +328,9 @@ __device__ void finalize_pair(PairState *st_g, const AlignConst *ac_g, const dou
 
 static_assert(kRedThreads == 256 && R_END == 48 && R_END <= kRedVals, "reduction layout");
 
+// ONE: every thread has at most one query (nblk * kRedThreads covers the
+// largest cloud), so there is no loop over queries around the 48 sums.
+template <bool ONE>
 __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
 {
     const int b = blockIdx.y;
@@ -350,8 +353,7 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
 #pragma unroll
     for (int k = 0; k < R_END; ++k) acc[k] = 0.0;
     const long long end = (long long)cd.pt_base + cd.n;
-    for (long long j = (long long)cd.pt_base + (long long)blockIdx.x * kRedThreads + threadIdx.x; j < end;
-         j += (long long)a.nblk * kRedThreads) {
+    auto add_query = [&](long long j) {
         const float4 zq = a.qpts[j];
         const int4 qm = a.map.qmap[j];  // (t, cluster size, pieces, first slot)
         const double z[3] = {T[0] * zq.x + T[1] * zq.y + T[2] * zq.z + T[3],
@@ -403,7 +405,7 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
                 S5 += (double)sv[u][5];
             }
         }
-        if (nj == 0) continue;
+        if (nj == 0) return;
         const double Dt[3] = {D0 * isc, D1 * isc, D2 * isc};
         const double S6[6] = {S0 * ia, S1 * ia, S2 * ia, S3 * ia, S4 * ia, S5 * ia};
         acc[R_F] += Wt;
@@ -446,7 +448,14 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
         for (int r = 0; r < 3; ++r)
 #pragma unroll
             for (int k = 0; k < 3; ++k) acc[R_HWV + 3 * r + k] += ZA[r][k] - 0.5 * Dx[r][k] * il2;
+    };
+    const long long j0 = (long long)cd.pt_base + (long long)blockIdx.x * kRedThreads + threadIdx.x;
+    if (ONE) {
+        if (j0 < end) add_query(j0);
+    } else {
+        for (long long j = j0; j < end; j += (long long)a.nblk * kRedThreads) add_query(j);
     }
+
 
     // block reduction, 24 values at a time through LDS: every thread stores
     // its 24 values; thread (value kv = t / 8, stripe s = t % 8), t < 192,
@@ -545,7 +554,10 @@ __global__ __launch_bounds__(kRedThreads) void reduce_finish_kernel(const Reduce
 
 void launch_reduce(const ReduceArgs &a, int B, hipStream_t s)
 {
-    hipLaunchKernelGGL(reduce_kernel, dim3(a.nblk, B), dim3(kRedThreads), 0, s, a);
+    if (a.one_query)
+        hipLaunchKernelGGL(reduce_kernel<true>, dim3(a.nblk, B), dim3(kRedThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(reduce_kernel<false>, dim3(a.nblk, B), dim3(kRedThreads), 0, s, a);
     hipLaunchKernelGGL(reduce_finish_kernel, dim3(B), dim3(kRedThreads), 0, s, a);
 }
 

@@ -192,3 +192,33 @@ def test_invalid_arguments_raise(cvo):
         cvo.cvo_evaluate(Xn, Z, np.eye(4), 0.1, U, V, p.spec)
     with pytest.raises(ValueError):
         cvo.cvo_evaluate(X, Z, np.eye(4), 0.1, None, None, p.spec)
+
+
+def test_large_cloud_self_pairs_closed_form(cvo):
+    """A cloud of 150,000 points (more than the reduction covers with one
+    query per thread, so its blocks loop over queries): a unit lattice and a
+    copy of it moved by < 0.07 per point, at ell = 0.1, cutoff 0.3.  Every
+    point pairs with its own copy only, so |P| = N and F, the gradient and
+    dF/dell are plain sums over the N offsets (eq. (7) with no features),
+    evaluated here in FP64."""
+    rng = np.random.default_rng(77)
+    g = np.stack(np.meshgrid(np.arange(50), np.arange(60), np.arange(50), indexing="ij"), -1).reshape(-1, 3)
+    x = g.astype(np.float32)
+    z = (g + rng.uniform(-0.04, 0.04, g.shape)).astype(np.float32)
+    assert x.shape[0] == 150000
+    ell = 0.1
+    X, Z = torch.from_numpy(x).cuda(), torch.from_numpy(z).cuda()
+    r = cvo.cvo_evaluate(X, Z, np.eye(4), ell, None, None, [])
+    d = x.astype(np.float64) - z.astype(np.float64)
+    s = (d * d).sum(1)
+    w = np.exp(-s / (2 * ell * ell))
+    zz = z.astype(np.float64)
+    v_terms = w[:, None] * d / ell ** 2
+    om_terms = w[:, None] * np.cross(zz, d) / ell ** 2
+    assert r["n_pairs"] == x.shape[0]
+    assert r["F"] == pytest.approx(w.sum(), rel=1e-6)
+    grad = np.asarray(r["grad"])
+    ref = np.concatenate([om_terms.sum(0), v_terms.sum(0)])
+    scale = np.concatenate([np.abs(om_terms).sum(0), np.abs(v_terms).sum(0)])
+    assert np.all(np.abs(grad - ref) <= 1e-5 * scale), (grad, ref)
+    assert r["dF_dell"] == pytest.approx((w * s).sum() / ell ** 3, rel=1e-5)
