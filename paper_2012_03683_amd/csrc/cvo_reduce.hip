@@ -369,41 +369,26 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
         acc[R_ZZ + 4] += z[1] * z[2];
         acc[R_ZZ + 5] += z[2] * z[2];
         // the query's partial moments of its cluster's pieces, in piece
-        // order: piece k's is at slot first + k n, so the loads of four
-        // pieces are independent and in flight together
+        // order: piece k's is at slot first + k n.  One piece per loop trip:
+        // the other queries' threads keep the memory system busy, and
+        // unrolling the loop with predicated loads (2, 4, ... pieces in
+        // flight) was slower at every density
         int nj = 0;
         double Wt = 0.0, D0 = 0.0, D1 = 0.0, D2 = 0.0;
         double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0, S5 = 0.0;
-        constexpr int kU = 4;
-        for (int k0 = 0; k0 < qm.z; k0 += kU) {
-            int c[kU];
-            double w[kU], d[kU][3];
-            float sv[kU][6];
-#pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const bool ok = k0 + u < qm.z;
-                const long long o = (long long)qm.w + (long long)(k0 + u) * qm.y;
-                c[u] = ok ? a.cnt[o] : 0;
-                w[u] = ok ? a.W[o] : 0.0;
-#pragma unroll
-                for (int q = 0; q < 3; ++q) d[u][q] = ok ? a.D[3 * o + q] : 0.0;
-#pragma unroll
-                for (int q = 0; q < 6; ++q) sv[u][q] = ok ? a.S[6 * o + q] : 0.0f;
-            }
-#pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                nj += c[u];
-                Wt += w[u];
-                D0 += d[u][0];
-                D1 += d[u][1];
-                D2 += d[u][2];
-                S0 += (double)sv[u][0];
-                S1 += (double)sv[u][1];
-                S2 += (double)sv[u][2];
-                S3 += (double)sv[u][3];
-                S4 += (double)sv[u][4];
-                S5 += (double)sv[u][5];
-            }
+        for (int k = 0; k < qm.z; ++k) {
+            const long long o = (long long)qm.w + (long long)k * qm.y;
+            nj += a.cnt[o];
+            Wt += a.W[o];
+            D0 += a.D[3 * o + 0];
+            D1 += a.D[3 * o + 1];
+            D2 += a.D[3 * o + 2];
+            S0 += (double)a.S[6 * o + 0];
+            S1 += (double)a.S[6 * o + 1];
+            S2 += (double)a.S[6 * o + 2];
+            S3 += (double)a.S[6 * o + 3];
+            S4 += (double)a.S[6 * o + 4];
+            S5 += (double)a.S[6 * o + 5];
         }
         if (nj == 0) return;
         const double Dt[3] = {D0 * isc, D1 * isc, D2 * isc};
