@@ -347,7 +347,7 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const ReduceArgs a)
     const double isc = 1.0 / sqrt(ascale), ia = 1.0 / ascale;
     const double il2 = 1.0 / (ell * ell), il4 = il2 * il2;
 
-    // every accumulator index below is a compile-time constant, so the 40
+    // every accumulator index below is a compile-time constant, so the 48
     // values stay in registers
     double acc[R_END];
 #pragma unroll
