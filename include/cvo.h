@@ -391,8 +391,8 @@ cvo_status cvo_set_tuning(cvo_handle h, const cvo_tuning *in);
 
 /* Project-written autotuner of the bin (grid cell) and tile (query cluster)
  * sizes.  Times the pair pass of (X, Z, spec, kp, T) under each view shape of
- * a search space -- cluster rule (octree, chunks) x points per cluster (16,
- * 32, 64) x cell edge (0.5, 1.0 r_c) x cluster edge cap (0.5, 1.0, 1.5 r_c),
+ * a search space -- chunk clusters x points per cluster (16, 32, 64) x cell
+ * edge (0.35, 0.5, 1.0 r_c) x cluster edge cap (0.3, 0.5, 1.0, 1.5 r_c),
  * median of 3 timed launches after one untimed -- and keeps the fastest:
  *   - as the handle's one-shot shape (cluster_max, cell_factor,
  *     cluster_factor, cluster_rule; the other tuning fields are unchanged),

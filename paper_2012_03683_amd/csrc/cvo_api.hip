@@ -1853,10 +1853,12 @@ cvo_status cvo_autotune(cvo_handle h, const cvo_cloud *X, const cvo_cloud *Z, co
         float best_ms = INFINITY;
         double npairs = -1.0;
         try {
-            for (int rule : {CVO_CLUSTER_CHUNKS, CVO_CLUSTER_OCTREE})
+            // chunk clusters only (the octree rule ties with them at best), with
+            // the finer cells and tighter clusters that the densest bands favour
+            for (int rule : {CVO_CLUSTER_CHUNKS})
                 for (int cm : {16, 32, 64})
-                    for (double cell : {0.5, 1.0})
-                        for (double cf : {0.5, 1.0, 1.5}) {
+                    for (double cell : {0.35, 0.5, 1.0})
+                        for (double cf : {0.3, 0.5, 1.0, 1.5}) {
                             cvo_tuning t = base;
                             t.cluster_rule = rule;
                             t.cluster_max = cm;

@@ -45,8 +45,8 @@ def test_autotune_choice_changes_speed_not_results(cvo, clean):
     base = cvo.cvo_get_tuning()
     chosen = cvo.cvo_autotune(X, Z, p.T_gt, 0.1, U, V, p.spec)
     print("autotune chose", chosen, flush=True)
-    assert chosen["cluster_max"] in (16, 32, 64) and chosen["cell_factor"] in (0.5, 1.0)
-    assert chosen["cluster_factor"] in (0.5, 1.0, 1.5) and chosen["cluster_rule"] in (0, 1)
+    assert chosen["cluster_max"] in (16, 32, 64) and chosen["cell_factor"] in (0.35, 0.5, 1.0)
+    assert chosen["cluster_factor"] in (0.3, 0.5, 1.0, 1.5) and chosen["cluster_rule"] == 1
     assert chosen["adaptive"] == base["adaptive"] and chosen["unroll"] == base["unroll"]
     assert cvo.cvo_get_tuning() == chosen
     g = cvo.cvo_evaluate(X, Z, p.T_gt, 0.1, U, V, p.spec)
