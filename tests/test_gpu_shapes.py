@@ -27,6 +27,8 @@ pytestmark = pytest.mark.gpu
 # one-shot default and a dense one)
 SHAPES = [(32, 0.35, 0.3, 1), (32, 0.35, 0.5, 1), (32, 0.5, 1.0, 1), (16, 0.5, 1.0, 1), (16, 1.0, 1.0, 1),
           (16, 0.5, 1.5, 1), (32, 0.5, 0.5, 1), (16, 1.0, 1.5, 1),
+          # corners of the autotuner's search space
+          (64, 0.35, 0.3, 1), (16, 0.35, 1.5, 1), (64, 1.0, 1.5, 1),
           (16, 1.0, 0.5, 0), (64, 0.5, 0.5, 0),
           # the finest cells allowed: a neighbourhood spans more than 64 rows of
           # cells, so the pass measures its rows in several batches
