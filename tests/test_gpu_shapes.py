@@ -22,17 +22,13 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 # (points per cluster, cell edge / r_c, cluster edge cap / r_c, cluster
-# rule): the shapes the density classes select (chunk clusters), dense to
-# sparse, two shapes of earlier class tables, and two octree shapes (the
-# one-shot default and a dense one)
-SHAPES = [(32, 0.35, 0.3, 1), (32, 0.35, 0.5, 1), (32, 0.5, 1.0, 1), (16, 0.5, 1.0, 1), (16, 1.0, 1.0, 1),
-          (16, 0.5, 1.5, 1), (32, 0.5, 0.5, 1), (16, 1.0, 1.5, 1),
-          # corners of the autotuner's search space
-          (64, 0.35, 0.3, 1), (16, 0.35, 1.5, 1), (64, 1.0, 1.5, 1),
-          (16, 1.0, 0.5, 0), (64, 0.5, 0.5, 0),
-          # the finest cells allowed: a neighbourhood spans more than 64 rows of
-          # cells, so the pass measures its rows in several batches
-          (32, 0.25, 1.0, 1)]
+# rule): every chunk-cluster shape of the autotuner's search space (which
+# holds the built-in density table's shapes), two octree shapes (the one-shot
+# default and a dense one), and the finest cells allowed: a neighbourhood then
+# spans more than 64 rows of cells, so the pass measures its rows in several
+# batches
+SHAPES = ([(cm, cell, cf, 1) for cm in (16, 32, 64) for cell in (0.35, 0.5, 1.0) for cf in (0.3, 0.5, 1.0, 1.5)]
+          + [(16, 1.0, 0.5, 0), (64, 0.5, 0.5, 0), (32, 0.25, 1.0, 1)])
 
 
 @pytest.fixture(scope="module")
