@@ -34,6 +34,12 @@ constexpr int kRedThreads = 256;
 
 enum Status { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAX_ITER = 2, ST_NO_OVERLAP = 3, ST_STATIONARY = 4 };
 
+// Holds a wave-uniform value in scalar registers at this point, so its load
+// is issued here (with the others of its round) and not sunk past a branch.
+__device__ __forceinline__ void in_sgpr(int v) { asm volatile("" ::"s"(v)); }
+__device__ __forceinline__ void in_sgpr(double v) { asm volatile("" ::"s"(v)); }
+__device__ __forceinline__ void in_sgpr(long long v) { asm volatile("" ::"s"(v)); }
+
 // Per-pair registration state, resident on the device for the whole ascent.
 struct alignas(16) PairState {
     double T[12];        // current pose [R|t], maps the Z frame into the X frame

@@ -181,26 +181,66 @@ void pair_pass_kernel(const PairPassArgs a)
     // one piece per wave; pieces are ordered heaviest first, so the largest
     // pieces are dispatched first and the light ones fill in behind them
     {
+        // The prologue's loads are requested in two dependent rounds: the
+        // piece record (its index clamped, so the load stays in bounds before
+        // the range check), then together the pair's flags, pose, lengthscale
+        // and grid.  The query row follows the exit test of finished pairs, in
+        // the round of the first cell-table reads.
         const int tk = wave_uniform(blockIdx.x * kWavesPerBlock + wv);
-        if (tk >= a.npieces) return;
-        const PieceRec rec = a.recs[tk];
+        const int npieces = a.npieces;
+        const PieceRec rec = a.recs[min(tk, npieces - 1)];
         const int4 pc = rec.pc;
         const int b = wave_uniform(rec.b);
         const PairState *st = a.state + b;
-        if (st->done || st->pause) return;
-
         const double *P = a.pose_is_inverse ? st->Tinv : st->T;
         double Pm[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) Pm[k] = P[k];
         const double ell = st->ell;
+        const int2 cl = make_int2(rec.first, rec.n);
+        const double4 g = rec.geo;
+        const GridDesc gd = a.grids[b];
+        __builtin_amdgcn_sched_barrier(0);  // (the exit test below must not be scheduled between these loads)
+        const int skip = st->done | st->pause;
+
+#pragma unroll
+        for (int k = 0; k < 12; ++k) in_sgpr(Pm[k]);
+        in_sgpr(ell);
+        in_sgpr(pc.y), in_sgpr(pc.z), in_sgpr(pc.w);
+        in_sgpr(cl.x), in_sgpr(cl.y);
+        in_sgpr(g.x), in_sgpr(g.y), in_sgpr(g.z), in_sgpr(g.w);
+        in_sgpr(gd.ox), in_sgpr(gd.oy), in_sgpr(gd.oz), in_sgpr(gd.inv_h);
+        in_sgpr(gd.nx), in_sgpr(gd.ny), in_sgpr(gd.nz), in_sgpr(gd.cell_base), in_sgpr(gd.n);
+        in_sgpr(a.kappa);
+        in_sgpr((long long)a.qpts), in_sgpr((long long)a.qfeat);
+        if (tk >= npieces || skip) return;
+
+        // query point owned by this lane; SUB sub-streams share the candidates
+        const int n = cl.y;
+        const int np2 = (n <= 1) ? 1 : (1 << (32 - __clz(n - 1)));
+        const int lg = __ffs(np2) - 1;
+        const int t = lane & (np2 - 1);
+        const int qs = lane >> lg;
+        const int SUB = kWave >> lg;
+        const bool active = t < n;
+        const int pq = cl.x + (active ? t : 0);
+        const float4 zq = a.qpts[pq];  // (reloaded on the rare exact-recheck path)
+        float vf[VF];
+#pragma unroll
+        for (int f = 0; f < VF / 4; ++f) vf[4 * f] = vf[4 * f + 1] = vf[4 * f + 2] = vf[4 * f + 3] = 0.0f;
+#pragma unroll
+        for (int f = 0; f < F4; ++f) {
+            const float4 v4 = reinterpret_cast<const float4 *>(a.qfeat)[(long long)pq * F4 + f];
+            vf[4 * f + 0] = v4.x;
+            vf[4 * f + 1] = v4.y;
+            vf[4 * f + 2] = v4.z;
+            vf[4 * f + 3] = v4.w;
+        }
+
         const double ascale = 1.4426950408889634 / (2.0 * ell * ell);  // log2(e) / (2 ell^2)
         const double sc = uniform_d(sqrt(ascale));
         const double rc = a.kappa * ell;
         const double rc2 = rc * rc;
-        const int2 cl = make_int2(rec.first, rec.n);
-        const double4 g = rec.geo;
-        const GridDesc gd = a.grids[b];
         const Neighbourhood nb = neighbourhood(Pm, g, rc, cut, gd);
         const double cx = uniform_d(nb.cx), cy = uniform_d(nb.cy), cz = uniform_d(nb.cz);
 
@@ -218,33 +258,12 @@ void pair_pass_kernel(const PairPassArgs a)
             cull2 = uniform_f((float)(nb.Rm * nb.Rm * ascale));
         }
 
-        // query point owned by this lane; SUB sub-streams share the candidates
-        const int n = cl.y;
-        const int np2 = (n <= 1) ? 1 : (1 << (32 - __clz(n - 1)));
-        const int lg = __ffs(np2) - 1;
-        const int t = lane & (np2 - 1);
-        const int qs = lane >> lg;
-        const int SUB = kWave >> lg;
-        const bool active = t < n;
-        const int pq = cl.x + (active ? t : 0);
-        const float4 zq = a.qpts[pq];  // (reloaded on the rare exact-recheck path)
         const double zpx = Pm[0] * zq.x + Pm[1] * zq.y + Pm[2] * zq.z + Pm[3];
         const double zpy = Pm[4] * zq.x + Pm[5] * zq.y + Pm[6] * zq.z + Pm[7];
         const double zpz = Pm[8] * zq.x + Pm[9] * zq.y + Pm[10] * zq.z + Pm[11];
         const float zrx = (float)((zpx - cx) * sc);
         const float zry = (float)((zpy - cy) * sc);
         const float zrz = (float)((zpz - cz) * sc);
-        float vf[VF];
-#pragma unroll
-        for (int f = 0; f < VF / 4; ++f) vf[4 * f] = vf[4 * f + 1] = vf[4 * f + 2] = vf[4 * f + 3] = 0.0f;
-#pragma unroll
-        for (int f = 0; f < F4; ++f) {
-            const float4 v4 = reinterpret_cast<const float4 *>(a.qfeat)[(long long)pq * F4 + f];
-            vf[4 * f + 0] = v4.x;
-            vf[4 * f + 1] = v4.y;
-            vf[4 * f + 2] = v4.z;
-            vf[4 * f + 3] = v4.w;
-        }
 
         double W = 0.0, Dx = 0.0, Dy = 0.0, Dz = 0.0;
         float S00 = 0.f, S01 = 0.f, S02 = 0.f, S11 = 0.f, S12 = 0.f, S22 = 0.f;
