@@ -63,7 +63,8 @@ typedef enum {
     CVO_OK = 0,
     CVO_ERR_INVALID_ARGUMENT = 1, /* bad sizes, pointers, non-finite or non-positive parameters */
     CVO_ERR_OUT_OF_MEMORY = 2,    /* device allocation failed */
-    CVO_ERR_DEVICE = 3,           /* a HIP runtime error; message kept */
+    CVO_ERR_DEVICE = 3,           /* a HIP runtime error, or a registration whose device state stopped
+                                     advancing (a launched batch left a running pair at its step); message kept */
     CVO_ERR_UNSUPPORTED = 4       /* e.g. feature layout beyond the compiled limits */
 } cvo_status;
 

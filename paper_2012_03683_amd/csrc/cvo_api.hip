@@ -1230,6 +1230,12 @@ void align_many(cvo_context *ctx, const std::vector<CloudPtrs> &X, const std::ve
     for (int b = 0; b < B; ++b) ell_build[b] = prm[b].ell_init;
     bool probe = adapt;
     std::vector<PairState> now(B);
+    // Every launched iteration either ends a running pair or advances its
+    // step count, so a batch after which a pair that was running has done
+    // neither means the device state is not what the host expects: an error,
+    // not another batch (the loop below otherwise ends only when every pair
+    // is done).
+    std::vector<PairState> ref = st;
     for (;;) {
         if (probe) {
             enqueue_iteration(ctx, p, 1, d_trace, trace_rows, ctx->profiling);
@@ -1263,6 +1269,11 @@ void align_many(cvo_context *ctx, const std::vector<CloudPtrs> &X, const std::ve
         }
         ctx->download(now.data(), p.d_state, sizeof(PairState) * B);
         if (ctx->profiling) ctx->harvest_events();
+        for (int b = 0; b < B; ++b)
+            if (!ref[b].done && !ref[b].pause && !now[b].done && now[b].it <= ref[b].it)
+                throw CvoError(CVO_ERR_DEVICE, "pair " + std::to_string(b) +
+                                                   ": a launched batch of iterations left it running at step " +
+                                                   std::to_string(now[b].it));
         bool all_done = true, rebuild = false, changed = false;
         std::vector<ViewShape> shape = p.shape;
         for (int b = 0; b < B; ++b) {
@@ -1285,6 +1296,7 @@ void align_many(cvo_context *ctx, const std::vector<CloudPtrs> &X, const std::ve
         if (all_done) break;
         if (rebuild) build_views(ctx, p, X, Z, ell_build, shape);
         if (changed) ctx->upload(p.d_state, now.data(), sizeof(PairState) * B);
+        ref = now;
     }
     final_state = now;
     if (ctx->profiling)
