@@ -1,7 +1,8 @@
 // cvo_pairs.hip -- the pair pass: the truncated double sum of eq. (7) and its
 // per-query moments, for one or many point-cloud pairs in one launch.
 //
-// Work decomposition (one 64-wide wavefront per query cluster):
+// Work decomposition (one 64-wide wavefront per piece: every np-th chunk of
+// 64 candidates of one query cluster, np set per cluster at planning time):
 //   * The cluster's n <= 64 query points are transformed into the reference
 //     frame once (FP64), then re-expressed relative to the transformed
 //     cluster centre c' and scaled by sqrt(a), a = log2(e) / (2 ell^2), in

@@ -317,15 +317,6 @@ __device__ __forceinline__ void finalize_local(PairState &st, const AlignConst &
     if (ac.adaptive && st.cls_built >= 0 && density_class(np * ac.inv_m, ac.cls_t) < st.cls_built) st.pause = 1;
 }
 
-__device__ void finalize_pair(PairState *st_g, const AlignConst *ac_g, const double *tot, double *trace,
-                              long long trace_rows, int mode)
-{
-    PairState st = *st_g;
-    const AlignConst ac = *ac_g;
-    finalize_local(st, ac, tot, trace, trace_rows, mode);
-    *st_g = st;
-}
-
 static_assert(kRedThreads == 256 && R_END == 48 && R_END <= kRedVals, "reduction layout");
 
 // ONE: every thread has at most one query (nblk * kRedThreads covers the
