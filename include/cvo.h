@@ -102,7 +102,7 @@ typedef enum {
 typedef struct {
     const float *xyz;  /* device, n x 3 */
     const float *feat; /* device, n x D (D from the feature spec); may be NULL when D = 0 */
-    int64_t n;         /* number of points, >= 0 */
+    int64_t n;         /* number of points, 0 <= n < 2^30 (else CVO_ERR_INVALID_ARGUMENT, before any device work) */
 } cvo_cloud;
 
 /* Feature blocks l(x) = (u_1, u_2, ...) in V_1 x V_2 x ... (Sec. III-B).

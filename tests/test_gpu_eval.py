@@ -194,18 +194,44 @@ def test_invalid_arguments_raise(cvo):
         cvo.cvo_evaluate(X, Z, np.eye(4), 0.1, None, None, p.spec)
 
 
-def test_large_cloud_self_pairs_closed_form(cvo):
-    """A cloud of 150,000 points (more than the reduction covers with one
-    query per thread, so its blocks loop over queries): a unit lattice and a
+def test_point_count_limit_rejected(cvo):
+    """Point counts outside [0, 2^30) are rejected on the host, before any
+    device work (the buffers here are small real ones; nothing reads them)."""
+    import ctypes as C
+    p = synth.tiny_cube(n=100)
+    X, Z, U, V = to_dev(p, torch)
+    cx, cz, keep, sp = cvo._prep(X, Z, U, V, p.spec)
+    kp = cvo.cvo_kernel_params(0.1, 1.0, 3.0)
+    Tp = cvo._pose(np.eye(4))
+    lib, h = cvo.load_library(), cvo.handle()
+    for bad in (1 << 30, (1 << 31) + 5, -1):
+        for which in ("X", "Z"):
+            cx.n, cz.n = X.shape[0], Z.shape[0]
+            (cx if which == "X" else cz).n = bad
+            F, n = C.c_double(), C.c_int64()
+            st = lib.cvo_inner_product(h, C.byref(cx), C.byref(cz), C.byref(sp), C.byref(kp), Tp.ctypes.data,
+                                       C.byref(F), C.byref(n))
+            assert st == cvo.CVO_ERR_INVALID_ARGUMENT, (bad, which, st)
+            assert "point count out of range" in lib.cvo_last_error(h).decode(), (bad, which)
+    del keep
+    # the handle still works afterwards
+    assert cvo.cvo_inner_product(X, Z, np.eye(4), 0.1, U, V, p.spec)[1] > 0
+
+
+@pytest.mark.parametrize("dims", [(50, 60, 50), (160, 160, 160)], ids=["150k", "4096k"])
+def test_large_cloud_self_pairs_closed_form(cvo, dims):
+    """Clouds of 150,000 and 4,096,000 points (more than the reduction covers
+    with one query per thread, so its blocks loop over queries; the larger one
+    also coarsens the grid to the library's cell cap): a unit lattice and a
     copy of it moved by < 0.07 per point, at ell = 0.1, cutoff 0.3.  Every
     point pairs with its own copy only, so |P| = N and F, the gradient and
     dF/dell are plain sums over the N offsets (eq. (7) with no features),
     evaluated here in FP64."""
     rng = np.random.default_rng(77)
-    g = np.stack(np.meshgrid(np.arange(50), np.arange(60), np.arange(50), indexing="ij"), -1).reshape(-1, 3)
+    g = np.stack(np.meshgrid(*(np.arange(k) for k in dims), indexing="ij"), -1).reshape(-1, 3)
     x = g.astype(np.float32)
     z = (g + rng.uniform(-0.04, 0.04, g.shape)).astype(np.float32)
-    assert x.shape[0] == 150000
+    assert x.shape[0] == dims[0] * dims[1] * dims[2]
     ell = 0.1
     X, Z = torch.from_numpy(x).cuda(), torch.from_numpy(z).cuda()
     r = cvo.cvo_evaluate(X, Z, np.eye(4), ell, None, None, [])
