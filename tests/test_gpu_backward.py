@@ -114,6 +114,32 @@ def test_learned_feature_workload(cvo):
             assert b["dell"] == pytest.approx(o["dF_dell"], rel=1e-5, abs=1e-5 * o["absF"] / p.ell)
 
 
+@pytest.mark.parametrize("ell", [0.5, 0.1])
+def test_full_size_stereo_backward_sampled(cvo, ell):
+    """The stereo-outdoor pair at full size (30k + 30k points, 5 SE + 19 LIN)
+    at its true pose, in a dense (ell = 0.5) and a sparse (ell = 0.1) band:
+    64 sampled rows of each of dX, dU, dZ and dV against the oracle's per-row
+    gradients, and dF/dell, F and |P| against the oracle's full evaluation."""
+    p = synth.stereo_pair(seed=1001)
+    X, Z, U, V = to_dev(p, torch)
+    b = cvo.cvo_inner_product_backward(X, Z, p.T_gt, ell, 1.0, U, V, p.spec)
+    F, n = cvo.cvo_inner_product(X, Z, p.T_gt, ell, U, V, p.spec)
+    o = oracle.evaluate(p.x, p.u, p.z, p.v, p.spec, ell, T=p.T_gt)
+    print("stereo backward ell", ell, "pairs", n, flush=True)
+    assert n == o["n_pairs"] > 0
+    assert abs(F - o["F"]) <= 1e-5 * o["absF"]
+    assert b["dell"] == pytest.approx(o["dF_dell"], rel=1e-5, abs=1e-5 * o["absF"] / ell)
+    rng = np.random.default_rng(5)
+    idx = rng.choice(p.x.shape[0], 64, replace=False)
+    dx, du = oracle.source_grad(p.x, p.u, p.z, p.v, p.spec, ell, idx, T=p.T_gt)
+    _cmp(b["dX"][idx], dx, "dX sample")
+    _cmp(b["dU"][idx], du, "dU sample")
+    jdx = rng.choice(p.z.shape[0], 64, replace=False)
+    dz, dv = oracle.target_grad(p.x, p.u, p.z, p.v, p.spec, ell, jdx, T=p.T_gt)
+    _cmp(b["dZ"][jdx], dz, "dZ sample")
+    _cmp(b["dV"][jdx], dv, "dV sample")
+
+
 def test_autograd_function(cvo):
     p = synth.random_pair(23, 600, 500, [synth.se_block(5, 0.25)], extent=0.4)
     T = synth.random_motion(np.random.default_rng(6), 1.0, 0.01)
