@@ -54,6 +54,15 @@ def test_cosine_stereo_and_learned_features(cvo):
     _check(cvo, q, q.T_eval, q.ell)
 
 
+@pytest.mark.parametrize("which,ell", [("stereo", 0.5), ("rgbd", 0.1)])
+def test_cosine_full_size(cvo, which, ell):
+    """The full stereo (30k + 30k, 5 SE + 19 LIN) and RGB-D (40k + 40k, 5 SE)
+    pairs at their true poses: the three inner products and the cosine."""
+    p = synth.stereo_pair(seed=1001) if which == "stereo" else synth.rgbd_pair(seed=1002)
+    g, o = _check(cvo, p, p.T_gt, ell)
+    print(which, "cos", g[0], o[0], flush=True)
+
+
 def test_cosine_sweep_peaks_at_alignment(cvo):
     """Fig. 3 of Sec. III-C: a stereo-shaped cloud rotated and translated
     against itself; cos(theta) and i_theta match the oracle at every sample and
