@@ -7,7 +7,10 @@ annealing of Sec. IV (Problem 1, eq. (1)):
   * RGB-D-indoor: 40,000 + 40,000 points, 5 SE features, 0.1 -> 0.05;
   * batched0 .. batched7: the first 8 of the 64 mixed pairs of the batched
     workload (N, M ~ U[2000, 60000], 5 SE + 19 LIN), each with its shape's
-    schedule.
+    schedule;
+  * stereo_adaptive, rgbd_adaptive: the stereo and RGB-D pairs registered
+    with the lengthscale as an optimisation variable (Sec. VI; stereo from
+    0.95 with a floor of 0.1, RGB-D from 0.1 with a floor of 0.02).
 Stored per workload: a SHA-256 of the generated inputs (so a test can tell
 that it regenerated the same clouds), the parameters, the converged pose,
 the report, and the per-iteration trace columns the GPU tests compare
@@ -15,7 +18,8 @@ the report, and the per-iteration trace columns the GPU tests compare
 
 Only ``paper_2012_03683_amd.synth`` (seeded input generators, no registration
 arithmetic) and ``oracle`` are called.  About 15 minutes on 8 cores for the
-two single pairs and 30 more for the batched subset.
+two single pairs, 30 more for the batched subset and 13 for the two adaptive
+runs.
 
 Usage: python tests/golden/make_full_size.py [stereo|rgbd ...]
 """
@@ -55,6 +59,14 @@ WORKLOADS = {
 }
 for _k in range(8):
     WORKLOADS[f"batched{_k}"] = (f"synth.batched_pairs(seed=1004, batch=64)[{_k}]", lambda k=_k: _batched(k))
+WORKLOADS["stereo_adaptive"] = WORKLOADS["stereo"]
+WORKLOADS["rgbd_adaptive"] = WORKLOADS["rgbd"]
+
+# parameters that replace the generator's defaults
+OVERRIDES = {
+    "stereo_adaptive": dict(ell_init=0.95, ell_min=0.1, max_iter=4000, ell_mode=1),
+    "rgbd_adaptive": dict(ell_init=0.1, ell_min=0.02, max_iter=4000, ell_mode=1),
+}
 
 
 def input_hash(p) -> str:
@@ -71,7 +83,7 @@ def input_hash(p) -> str:
 def run(name):
     desc, make = WORKLOADS[name]
     p = make()
-    params = dict(p.align)
+    params = dict(p.align, **OVERRIDES.get(name, {}))
     t0 = time.time()
     T, rep, tr = oracle.align(p.x, p.u, p.z, p.v, p.spec, params)
     sec = time.time() - t0

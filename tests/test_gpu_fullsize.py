@@ -4,7 +4,8 @@ eq. (1), with the annealing of Sec. IV).
 The oracle's runs of the stereo-outdoor pair (30k + 30k, 5 SE + 19 LIN,
 ell 0.95 -> 0.1) and the RGB-D-indoor pair (40k + 40k, 5 SE, 0.1 -> 0.05) are
 stored in golden/full_size_registrations.json by golden/make_full_size.py
-(it calls only the input generators and the oracle).  The test regenerates
+(it calls only the input generators and the oracle), and so are their runs
+with the lengthscale as an optimisation variable (Sec. VI).  The test regenerates
 the inputs, checks they hash to what the oracle was run on, then
   * registers them with cvo_align: same status and final lengthscale, and the
     converged pose within 1e-4 rad / 1e-4 m of the oracle's;
@@ -82,7 +83,32 @@ def test_full_size_converged_pose_matches_oracle(cvo, golden, which):
     print(which, "iterations", len(tr), len(g["trace"]["ell"]), "schedules agree through", agree, flush=True)
 
 
-@pytest.mark.parametrize("which", ["stereo", "rgbd"])
+@pytest.mark.parametrize("which", ["stereo_adaptive", "rgbd_adaptive"])
+def test_full_size_adaptive_matches_oracle(cvo, golden, which):
+    """The adaptive runs: same status, final lengthscale within 1e-4 (it is
+    the objective's maximiser, a continuous value), the converged pose within
+    1e-4 rad / 1e-4 m, and the lengthscale sequences agreeing to 1e-5 over the
+    first iterations."""
+    p, g = _pair(which, golden)
+    X, Z, U, V = to_dev(p, torch)
+    print(f"{which}: cvo_align at full size", flush=True)
+    T, rep, tr = cvo.cvo_align(X, Z, U, V, p.spec, g["params"], trace=True)
+    ang, dt = pose_error(T, np.array(g["T"]))
+    print(which, "gpu", rep, "oracle", g["report"], "pose deviation", ang, dt, flush=True)
+    assert rep["status"] == g["report"]["status"] == cvo.CVO_CONVERGED
+    assert rep["final_ell"] == pytest.approx(g["report"]["final_ell"], rel=1e-4)
+    assert ang < 1e-4 and dt < 1e-4
+    ello = np.array(g["trace"]["ell"])
+    n = min(len(tr), len(ello))
+    same = np.abs(tr[:n, 1] / ello[:n] - 1.0) <= 1e-5
+    agree = n if same.all() else int(np.argmin(same))
+    print(which, "iterations", len(tr), len(ello), "lengthscales agree through", agree, flush=True)
+    assert agree >= min(n, 5)
+    np.testing.assert_allclose(tr[:agree, 2], g["trace"]["F"][:agree], rtol=1e-5)
+    assert tr[0, 6] == g["trace"]["n_pairs"][0]
+
+
+@pytest.mark.parametrize("which", ["stereo", "rgbd", "stereo_adaptive", "rgbd_adaptive"])
 def test_full_size_replay_iterate_by_iterate(cvo, golden, which):
     p, g = _pair(which, golden)
     X, Z, U, V = to_dev(p, torch)
