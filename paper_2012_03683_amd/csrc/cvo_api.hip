@@ -845,7 +845,7 @@ Plan make_plan(cvo_context *ctx, const std::string &pre, const ClusterView &q, c
     pl.qmap = ctx->get_t<int4>(pre + ".qmap", std::max<long long>(q.ntot, 1));
     launch_plan_qmap(q.clus, pl.cpieces, pl.pieces, nc, pl.qmap, ctx->stream);
     bool in_tmp = false;
-    launch_radix_sort(key, val, ktmp, vtmp, hist, bsum2, P, 24, ctx->stream, &in_tmp);
+    launch_radix_sort(key, val, ktmp, vtmp, hist, bsum2, P, 16, ctx->stream, &in_tmp);
     pl.porder = in_tmp ? vtmp : val;
     pl.recs = ctx->get_t<PieceRec>(pre + ".recs", std::max(P, 1));
     launch_plan_records(pl.porder, pl.pieces, q.cpair, q.clus, q.cgeo, P, pl.recs, ctx->stream);

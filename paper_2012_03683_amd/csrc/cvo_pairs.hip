@@ -535,6 +535,17 @@ __global__ void plan_count(const PairPassArgs a, int work, int *npieces, int *cm
     }
 }
 
+// A piece's cost on 16 bits, non-decreasing in the cost: exact below 49152
+// (every piece of the default plan: n <= 64 queries x at most 576), then
+// 1024 steps per doubling.
+constexpr unsigned long long kCostLinear = 49152;
+__device__ __forceinline__ unsigned int piece_cost_code(unsigned long long cost)
+{
+    if (cost < kCostLinear) return (unsigned int)cost;
+    const double q = (log2((double)cost) - log2((double)kCostLinear)) * 1024.0;
+    return (unsigned int)min((double)kCostLinear + floor(q), 65535.0);
+}
+
 // Emit the pieces of each cluster (cluster-major) as (cluster, p, np), their
 // query counts (for the output-slot scan) and a sort key: the heaviest piece
 // gets the smallest key; the stable sort keeps a cluster's pieces together.
@@ -551,7 +562,7 @@ __global__ void plan_emit(const PairPassArgs a, const int *npieces, const int *p
             pieces[pb + p] = make_int4(c, p, np, 0);
             pn[pb + p] = n;
             const unsigned long long cost = (unsigned long long)n * (unsigned long long)(cand + 64);
-            key[pb + p] = 0xffffffULL - (cost > 0xffffffULL ? 0xffffffULL : cost);  // 24-bit key
+            key[pb + p] = 0xffffULL - (unsigned long long)piece_cost_code(cost);  // 16-bit key
             val[pb + p] = pb + p;
         }
     }
