@@ -37,6 +37,8 @@ SPECS = {
     "se5": [synth.se_block(5, 0.2)],
     "se5_lin19": [synth.se_block(5, 0.2), synth.lin_block(19)],
     "lin32": [synth.lin_block(32)],
+    "se20_lin19": [synth.se_block(20, 0.8), synth.lin_block(19)],
+    "lin40": [synth.lin_block(40)],
 }
 
 

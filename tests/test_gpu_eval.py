@@ -54,6 +54,11 @@ SPECS = {
     "se2_se3": [synth.se_block(2, 0.3), synth.se_block(3, 0.5, sigma=1.3)],
     "lin3": [synth.lin_block(3)],
     "se7_lin1": [synth.se_block(7, 0.4), synth.lin_block(1)],
+    # the wide compiled kernels: 16 and 32 SE columns, 64 LIN columns
+    "se12": [synth.se_block(12, 0.6)],
+    "se20_lin19": [synth.se_block(20, 0.8), synth.lin_block(19)],
+    "se16_lin32": [synth.se_block(16, 0.7), synth.lin_block(32)],
+    "lin40": [synth.lin_block(40)],
 }
 
 
