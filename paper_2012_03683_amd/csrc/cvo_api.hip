@@ -251,9 +251,13 @@ struct cvo_context {
         HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
         return e;
     }
-    void harvest_events()
+    // adds the times of the first `count` pending launches (all by default;
+    // their events must have completed)
+    void harvest_events(size_t count = SIZE_MAX)
     {
-        for (auto &pr : ev_pending) {
+        count = std::min(count, ev_pending.size());
+        for (size_t k = 0; k < count; ++k) {
+            auto &pr = ev_pending[k];
             float ms = 0.f;
             HIP_OK(hipEventElapsedTime(&ms, pr.first, pr.second));
             timing.pair_ms += ms;
@@ -261,7 +265,7 @@ struct cvo_context {
             ev_free.push_back(pr.first);
             ev_free.push_back(pr.second);
         }
-        ev_pending.clear();
+        ev_pending.erase(ev_pending.begin(), ev_pending.begin() + (long)count);
     }
     hipStream_t capture_stream()
     {
@@ -1236,6 +1240,7 @@ void align_many(cvo_context *ctx, const std::vector<CloudPtrs> &X, const std::ve
     // not another batch (the loop below otherwise ends only when every pair
     // is done).
     std::vector<PairState> ref = st;
+    size_t timed_done = 0;  // pending timed launches of batches already waited for
     for (;;) {
         if (probe) {
             enqueue_iteration(ctx, p, 1, d_trace, trace_rows, ctx->profiling);
@@ -1267,8 +1272,10 @@ void align_many(cvo_context *ctx, const std::vector<CloudPtrs> &X, const std::ve
         } else {
             for (int u = 0; u < U; ++u) enqueue_iteration(ctx, p, 1, d_trace, trace_rows, ctx->profiling);
         }
+        // the previous batch's launch times are read while this batch runs
+        if (ctx->profiling) ctx->harvest_events(timed_done);
         ctx->download(now.data(), p.d_state, sizeof(PairState) * B);
-        if (ctx->profiling) ctx->harvest_events();
+        timed_done = ctx->ev_pending.size();
         for (int b = 0; b < B; ++b)
             if (!ref[b].done && !ref[b].pause && !now[b].done && now[b].it <= ref[b].it)
                 throw CvoError(CVO_ERR_DEVICE, "pair " + std::to_string(b) +
@@ -1293,7 +1300,10 @@ void align_many(cvo_context *ctx, const std::vector<CloudPtrs> &X, const std::ve
             changed = true;
         }
         probe = false;
-        if (all_done) break;
+        if (all_done) {
+            if (ctx->profiling) ctx->harvest_events();
+            break;
+        }
         if (rebuild) build_views(ctx, p, X, Z, ell_build, shape);
         if (changed) ctx->upload(p.d_state, now.data(), sizeof(PairState) * B);
         ref = now;
